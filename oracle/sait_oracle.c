@@ -1,0 +1,799 @@
+/*
+ * SAIT CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously-correct FP64 reference for everything the GPU
+ * library computes.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this file's library; the product
+ * (the HIP library and its Python binding) never links, imports or calls
+ * it, and shares no code with it.
+ *
+ * Paper: Z. Lu, "A sparse approximate inverse for triangular matrices based
+ * on Jacobi iteration" (arXiv 2106.12836).  Each function names the passage
+ * it follows.  Compiled with -ffp-contract=off: every a*b+c below is two
+ * roundings, exactly as written.
+ *
+ * Conventions: square CSR matrices, int32 row pointers and column indices
+ * (columns sorted, unique per row), double values.  Functions that produce
+ * a matrix allocate its three arrays with malloc and hand them back through
+ * out-pointers; the caller releases them with or_free().
+ *
+ * Readings of the paper taken here (where it is silent or ambiguous):
+ *   - the SAIT loop count m is the highest power of the iteration matrix
+ *     kept (Eq. M_m; Alg. 1 runs m passes of M <- T~ M + I);
+ *   - threshold dropping keeps an entry iff |M_ij| > tau (Appendix A's
+ *     mask), applied to M before the final column scaling M <- M D^-1;
+ *     exact zeros are never stored;
+ *   - T~ = I - D^-1 T has a structurally zero diagonal (Sec. 2 defines it
+ *     as strictly triangular), off-diagonal T~_ij = -(fl(1/d_i) * T_ij);
+ *   - the optional per-row cap K (not in the paper) keeps the diagonal and
+ *     the K-1 largest magnitudes, ties to the smaller column;
+ *   - ILU(0) is Doolittle (unit lower L stored with its diagonal), IKJ order
+ *     (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 10.4);
+ *   - ILUT(tau, p) is Saad's dual-threshold ILUT (Alg. 10.6) with
+ *     tau_i = tau * ||a_i,*||_2, drop on |w_k| < tau_i, keep the p largest in
+ *     each of L and U (ties to the smaller column), exact zeros dropped;
+ *   - GMRES is right-preconditioned restarted GMRES with modified
+ *     Gram-Schmidt and Givens rotations (Saad Alg. 9.5 / 6.9); FGMRES stores
+ *     the preconditioned vectors (Saad Alg. 9.6).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_NOT_CONVERGED 1
+#define OR_E_INVALID -1
+#define OR_E_ZERO_PIVOT -2
+#define OR_E_NONFINITE -3
+#define OR_E_NOMEM -4
+
+void or_free(void *p) { free(p); }
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n, cap, nnz;
+    int32_t *rp, *ci;
+    double *v;
+} or_builder; /* row-by-row CSR builder */
+
+static int bld_init(or_builder *b, int64_t n, int64_t cap) {
+    b->n = n;
+    b->cap = cap > 16 ? cap : 16;
+    b->nnz = 0;
+    b->rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    b->ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)b->cap);
+    b->v = (double *)malloc(sizeof(double) * (size_t)b->cap);
+    if (!b->rp || !b->ci || !b->v) return OR_E_NOMEM;
+    b->rp[0] = 0;
+    return OR_OK;
+}
+
+static int bld_push(or_builder *b, int32_t col, double val) {
+    if (b->nnz == b->cap) {
+        int64_t nc = b->cap * 2;
+        int32_t *nci = (int32_t *)realloc(b->ci, sizeof(int32_t) * (size_t)nc);
+        if (!nci) return OR_E_NOMEM;
+        b->ci = nci;
+        double *nv = (double *)realloc(b->v, sizeof(double) * (size_t)nc);
+        if (!nv) return OR_E_NOMEM;
+        b->v = nv;
+        b->cap = nc;
+    }
+    if (b->nnz >= INT32_MAX) return OR_E_INVALID;
+    b->ci[b->nnz] = col;
+    b->v[b->nnz] = val;
+    b->nnz++;
+    return OR_OK;
+}
+
+static void bld_end_row(or_builder *b, int64_t i) { b->rp[i + 1] = (int32_t)b->nnz; }
+
+static void bld_free(or_builder *b) {
+    free(b->rp);
+    free(b->ci);
+    free(b->v);
+    b->rp = NULL;
+    b->ci = NULL;
+    b->v = NULL;
+}
+
+static void bld_give(or_builder *b, int32_t **rp, int32_t **ci, double **v) {
+    *rp = b->rp;
+    *ci = b->ci;
+    *v = b->v;
+    b->rp = NULL;
+    b->ci = NULL;
+    b->v = NULL;
+}
+
+static int cmp_int32(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Entry used when ranking by magnitude: larger |val| first, then smaller col. */
+typedef struct {
+    int32_t col;
+    double val;
+} or_entry;
+
+static int cmp_mag_desc(const void *a, const void *b) {
+    const or_entry *x = (const or_entry *)a, *y = (const or_entry *)b;
+    double ax = fabs(x->val), ay = fabs(y->val);
+    if (ax > ay) return -1;
+    if (ax < ay) return 1;
+    return (x->col > y->col) - (x->col < y->col);
+}
+
+static int cmp_col_asc(const void *a, const void *b) {
+    const or_entry *x = (const or_entry *)a, *y = (const or_entry *)b;
+    return (x->col > y->col) - (x->col < y->col);
+}
+
+/* ------------------------------------------------------------------ */
+/* ILU(0): Saad Alg. 10.4 (IKJ), pattern of A; "level-0 ILU" of Sec. 4. */
+/* ------------------------------------------------------------------ */
+int or_ilu0(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+            int32_t **Lrp, int32_t **Lci, double **Lv,
+            int32_t **Urp, int32_t **Uci, double **Uv) {
+    int64_t nnz = rp[n];
+    double *a = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    int64_t *dpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *where = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!a || !dpos || !where) { free(a); free(dpos); free(where); return OR_E_NOMEM; }
+    memcpy(a, v, sizeof(double) * (size_t)nnz);
+    for (int64_t j = 0; j < n; j++) where[j] = -1;
+    int st = OR_OK;
+    for (int64_t i = 0; i < n && st == OR_OK; i++) {
+        dpos[i] = -1;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            where[ci[p]] = p;
+            if (ci[p] == i) dpos[i] = p;
+        }
+        if (dpos[i] < 0) { st = OR_E_ZERO_PIVOT; }
+        for (int64_t p = rp[i]; p < rp[i + 1] && st == OR_OK; p++) {
+            int64_t k = ci[p];
+            if (k >= i) break; /* columns sorted: the L part comes first */
+            double piv = a[dpos[k]];
+            a[p] = a[p] / piv;              /* a_ik <- a_ik / a_kk */
+            for (int64_t q = dpos[k] + 1; q < rp[k + 1]; q++) {
+                int64_t j = ci[q];          /* a_kj, j > k */
+                if (where[j] >= 0) a[where[j]] = a[where[j]] - a[p] * a[q];
+            }
+        }
+        if (st == OR_OK) {
+            double d = a[dpos[i]];
+            if (d == 0.0) st = OR_E_ZERO_PIVOT;
+            else if (!isfinite(d)) st = OR_E_NONFINITE;
+        }
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) where[ci[p]] = -1;
+    }
+    if (st != OR_OK) { free(a); free(dpos); free(where); return st; }
+    or_builder L, U;
+    memset(&L, 0, sizeof(L));
+    memset(&U, 0, sizeof(U));
+    int64_t nl = 0;
+    for (int64_t i = 0; i < n; i++) nl += dpos[i] - rp[i];
+    if (bld_init(&L, n, nl + n) || bld_init(&U, n, nnz - nl)) {
+        bld_free(&L); bld_free(&U); free(a); free(dpos); free(where); return OR_E_NOMEM;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t p = rp[i]; p < dpos[i]; p++) bld_push(&L, ci[p], a[p]);
+        bld_push(&L, (int32_t)i, 1.0);
+        bld_end_row(&L, i);
+        for (int64_t p = dpos[i]; p < rp[i + 1]; p++) bld_push(&U, ci[p], a[p]);
+        bld_end_row(&U, i);
+    }
+    bld_give(&L, Lrp, Lci, Lv);
+    bld_give(&U, Urp, Uci, Uv);
+    free(a); free(dpos); free(where);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* ILUT(tau, p): Saad Alg. 10.6 (dual threshold).                       */
+/* ------------------------------------------------------------------ */
+int or_ilut(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+            double tau, int p,
+            int32_t **Lrp, int32_t **Lci, double **Lv,
+            int32_t **Urp, int32_t **Uci, double **Uv) {
+    if (p < 0 || !(tau >= 0.0)) return OR_E_INVALID;
+    double *w = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    char *present = (char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int32_t *cols = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    or_entry *sel = (or_entry *)malloc(sizeof(or_entry) * (size_t)(n > 0 ? n : 1));
+    double *udiag = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    or_builder L, U;
+    memset(&L, 0, sizeof(L));
+    memset(&U, 0, sizeof(U));
+    int st = OR_OK;
+    if (!w || !present || !cols || !sel || !udiag) st = OR_E_NOMEM;
+    if (st == OR_OK && (bld_init(&L, n, rp[n] + n) || bld_init(&U, n, rp[n] + n))) st = OR_E_NOMEM;
+    for (int64_t i = 0; i < n && st == OR_OK; i++) {
+        int64_t ncols = 0;
+        double nrm2 = 0.0;
+        for (int64_t q = rp[i]; q < rp[i + 1]; q++) {
+            int32_t j = ci[q];
+            w[j] = v[q];
+            present[j] = 1;
+            cols[ncols++] = j;
+            nrm2 = nrm2 + v[q] * v[q];
+        }
+        double tau_i = tau * sqrt(nrm2);
+        /* eliminate in increasing k over the (growing) set of columns < i */
+        int64_t kprev = -1;
+        for (;;) {
+            int64_t k = -1;
+            for (int64_t t = 0; t < ncols; t++) {
+                int64_t c = cols[t];
+                if (c < i && c > kprev && (k < 0 || c < k)) k = c;
+            }
+            if (k < 0) break;
+            kprev = k;
+            if (w[k] == 0.0) continue;
+            w[k] = w[k] / udiag[k];
+            if (fabs(w[k]) < tau_i) { w[k] = 0.0; continue; }
+            for (int64_t q = U.rp[k]; q < U.rp[k + 1]; q++) {
+                int32_t j = U.ci[q];
+                if (j <= k) continue; /* the diagonal of row k */
+                if (!present[j]) { present[j] = 1; w[j] = 0.0; cols[ncols++] = j; }
+                w[j] = w[j] - w[k] * U.v[q];
+            }
+        }
+        /* L part: j < i */
+        int64_t ns = 0;
+        for (int64_t t = 0; t < ncols; t++) {
+            int32_t j = cols[t];
+            if (j < i && w[j] != 0.0 && !(fabs(w[j]) < tau_i)) { sel[ns].col = j; sel[ns].val = w[j]; ns++; }
+        }
+        qsort(sel, (size_t)ns, sizeof(or_entry), cmp_mag_desc);
+        if (ns > p) ns = p;
+        qsort(sel, (size_t)ns, sizeof(or_entry), cmp_col_asc);
+        for (int64_t t = 0; t < ns; t++) bld_push(&L, sel[t].col, sel[t].val);
+        bld_push(&L, (int32_t)i, 1.0);
+        bld_end_row(&L, i);
+        /* diagonal */
+        double d = present[i] ? w[i] : 0.0;
+        if (d == 0.0) st = OR_E_ZERO_PIVOT;
+        else if (!isfinite(d)) st = OR_E_NONFINITE;
+        udiag[i] = d;
+        /* U part: j > i */
+        ns = 0;
+        for (int64_t t = 0; t < ncols; t++) {
+            int32_t j = cols[t];
+            if (j > i && w[j] != 0.0 && !(fabs(w[j]) < tau_i)) { sel[ns].col = j; sel[ns].val = w[j]; ns++; }
+        }
+        qsort(sel, (size_t)ns, sizeof(or_entry), cmp_mag_desc);
+        if (ns > p) ns = p;
+        qsort(sel, (size_t)ns, sizeof(or_entry), cmp_col_asc);
+        bld_push(&U, (int32_t)i, d);
+        for (int64_t t = 0; t < ns; t++) bld_push(&U, sel[t].col, sel[t].val);
+        bld_end_row(&U, i);
+        for (int64_t t = 0; t < ncols; t++) { w[cols[t]] = 0.0; present[cols[t]] = 0; }
+    }
+    free(w); free(present); free(cols); free(sel); free(udiag);
+    if (st != OR_OK) { bld_free(&L); bld_free(&U); return st; }
+    bld_give(&L, Lrp, Lci, Lv);
+    bld_give(&U, Urp, Uci, Uv);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Exact substitution (Sec. 1: forward / backward substitution).        */
+/* ------------------------------------------------------------------ */
+int or_lower_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                   const double *b, double *x) {
+    for (int64_t i = 0; i < n; i++) {
+        double s = b[i], d = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] < i) s = s - v[p] * x[ci[p]];
+            else if (ci[p] == i) d = v[p];
+        }
+        if (d == 0.0) return OR_E_ZERO_PIVOT;
+        x[i] = s / d;
+    }
+    return OR_OK;
+}
+
+int or_upper_solve(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                   const double *b, double *x) {
+    for (int64_t i = n - 1; i >= 0; i--) {
+        double s = b[i], d = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] > i) s = s - v[p] * x[ci[p]];
+            else if (ci[p] == i) d = v[p];
+        }
+        if (d == 0.0) return OR_E_ZERO_PIVOT;
+        x[i] = s / d;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* SAIT (Sec. 2-3; Alg. 1, 2, 3; Appendix A)                            */
+/* ------------------------------------------------------------------ */
+
+/* d_i and fl(1/d_i) of a triangular T; rejects missing, zero or
+ * non-finite diagonals (D^-1 must exist, Eq. Jacobi_iter). */
+static int sait_dinv(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *dinv) {
+    for (int64_t i = 0; i < n; i++) {
+        double d = 0.0;
+        int found = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++)
+            if (ci[p] == i) { d = v[p]; found = 1; }
+        if (!found || d == 0.0) return OR_E_ZERO_PIVOT;
+        if (!isfinite(d)) return OR_E_NONFINITE;
+        dinv[i] = 1.0 / d;
+    }
+    return OR_OK;
+}
+
+/*
+ * One pass of the Horner recursion (Eq. Recursive) with dropping:
+ *     W = T~ * Mprev + I,   T~ = I - D^-1 T   (diagonal structurally zero)
+ * then keep (i,j) iff |W_ij| > tau (Alg. 2 / Appendix A mask) -- or iff
+ * (i,j) lies in the pattern S when S is given (Alg. 3) -- and finally, if
+ * cap > 0, keep the diagonal plus the cap-1 largest |W_ij|.
+ * Row i of T~*M is formed the Gustavson way: for each l in T~ row i in
+ * increasing column order, add T~_il * M_l,* into a dense accumulator.
+ * Pattern mode (S != NULL): keep iff W_ij != 0 and (i,j) in S.
+ */
+static int sait_pass(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
+                     const double *dinv,
+                     const int32_t *Mrp, const int32_t *Mci, const double *Mv,
+                     double tau, int cap,
+                     const int32_t *Srp, const int32_t *Sci,
+                     double *acc, char *touched, int32_t *list, char *inS, or_entry *ent,
+                     or_builder *out) {
+    for (int64_t i = 0; i < n; i++) {
+        int64_t nl = 0;
+        for (int64_t p = Trp[i]; p < Trp[i + 1]; p++) {
+            int64_t l = Tci[p];
+            if (l == i) continue;                       /* T~_ii = 0 */
+            double tl = -(dinv[i] * Tv[p]);             /* T~_il */
+            for (int64_t q = Mrp[l]; q < Mrp[l + 1]; q++) {
+                int32_t j = Mci[q];
+                if (!touched[j]) { touched[j] = 1; acc[j] = 0.0; list[nl++] = j; }
+                acc[j] = acc[j] + tl * Mv[q];
+            }
+        }
+        /* + I */
+        if (!touched[i]) { touched[i] = 1; acc[i] = 0.0; list[nl++] = (int32_t)i; }
+        acc[i] = acc[i] + 1.0;
+        qsort(list, (size_t)nl, sizeof(int32_t), cmp_int32);
+        if (Srp) for (int64_t q = Srp[i]; q < Srp[i + 1]; q++) inS[Sci[q]] = 1;
+        int64_t ne = 0;
+        double wdiag = 0.0;
+        for (int64_t t = 0; t < nl; t++) {
+            int32_t j = list[t];
+            double w = acc[j];
+            int keep = Srp ? (inS[j] && w != 0.0) : (fabs(w) > tau);
+            if (j == i) { wdiag = w; continue; }         /* diagonal handled below */
+            if (keep) { ent[ne].col = j; ent[ne].val = w; ne++; }
+        }
+        if (Srp) for (int64_t q = Srp[i]; q < Srp[i + 1]; q++) inS[Sci[q]] = 0;
+        for (int64_t t = 0; t < nl; t++) touched[list[t]] = 0;
+        if (cap > 0 && ne > cap - 1) {
+            qsort(ent, (size_t)ne, sizeof(or_entry), cmp_mag_desc);
+            ne = cap - 1;
+            qsort(ent, (size_t)ne, sizeof(or_entry), cmp_col_asc);
+        }
+        /* emit in column order with the diagonal in its place */
+        int placed = 0;
+        for (int64_t t = 0; t <= ne; t++) {
+            if (!placed && (t == ne || ent[t].col > i)) {
+                if (bld_push(out, (int32_t)i, wdiag)) return OR_E_NOMEM;
+                placed = 1;
+            }
+            if (t < ne && bld_push(out, ent[t].col, ent[t].val)) return OR_E_NOMEM;
+        }
+        bld_end_row(out, i);
+    }
+    return OR_OK;
+}
+
+typedef struct {
+    double *acc;
+    char *touched, *inS;
+    int32_t *list;
+    or_entry *ent;
+    double *dinv;
+} sait_ws;
+
+static int ws_init(sait_ws *w, int64_t n) {
+    size_t m = (size_t)(n > 0 ? n : 1);
+    w->acc = (double *)malloc(sizeof(double) * m);
+    w->touched = (char *)calloc(m, 1);
+    w->inS = (char *)calloc(m, 1);
+    w->list = (int32_t *)malloc(sizeof(int32_t) * m);
+    w->ent = (or_entry *)malloc(sizeof(or_entry) * m);
+    w->dinv = (double *)malloc(sizeof(double) * m);
+    return (w->acc && w->touched && w->inS && w->list && w->ent && w->dinv) ? OR_OK : OR_E_NOMEM;
+}
+
+static void ws_free(sait_ws *w) {
+    free(w->acc); free(w->touched); free(w->inS); free(w->list); free(w->ent); free(w->dinv);
+}
+
+/* One unscaled pass, exported for step-by-step comparison:
+ * Mnext = drop(T~ * Mprev + I). */
+int or_sait_step(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
+                 const int32_t *Mrp, const int32_t *Mci, const double *Mv,
+                 double tau, int cap,
+                 int32_t **Orp, int32_t **Oci, double **Ov) {
+    if (!(tau >= 0.0 && tau < 1.0) || cap < 0) return OR_E_INVALID;
+    sait_ws w;
+    or_builder out;
+    int st = ws_init(&w, n);
+    if (st == OR_OK) st = sait_dinv(n, Trp, Tci, Tv, w.dinv);
+    if (st == OR_OK) st = bld_init(&out, n, Mrp[n] + n);
+    if (st == OR_OK) {
+        st = sait_pass(n, Trp, Tci, Tv, w.dinv, Mrp, Mci, Mv, tau, cap, NULL, NULL,
+                       w.acc, w.touched, w.list, w.inS, w.ent, &out);
+        if (st == OR_OK) bld_give(&out, Orp, Oci, Ov);
+        else bld_free(&out);
+    }
+    ws_free(&w);
+    return st;
+}
+
+/* Common driver for Alg. 2 (S == NULL after p passes: threshold) and Alg. 3. */
+static int sait_run(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
+                    double tau, int m, int cap, int p_pattern,
+                    int32_t **Orp, int32_t **Oci, double **Ov) {
+    sait_ws w;
+    int st = ws_init(&w, n);
+    if (st == OR_OK) st = sait_dinv(n, Trp, Tci, Tv, w.dinv);
+    /* M = I */
+    or_builder cur;
+    if (st == OR_OK) st = bld_init(&cur, n, n);
+    if (st != OR_OK) { ws_free(&w); return st; }
+    for (int64_t i = 0; i < n; i++) { bld_push(&cur, (int32_t)i, 1.0); bld_end_row(&cur, i); }
+    int32_t *Srp = NULL, *Sci = NULL;
+    /* Alg. 3 steps 2-4: p unrestricted passes, then S = pattern(M) */
+    for (int k = 0; k < p_pattern && st == OR_OK; k++) {
+        or_builder nxt;
+        st = bld_init(&nxt, n, cur.nnz + n);
+        if (st == OR_OK) st = sait_pass(n, Trp, Tci, Tv, w.dinv, cur.rp, cur.ci, cur.v, 0.0, 0,
+                                        NULL, NULL, w.acc, w.touched, w.list, w.inS, w.ent, &nxt);
+        bld_free(&cur);
+        cur = nxt;
+    }
+    if (st == OR_OK && p_pattern >= 0) {
+        Srp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+        Sci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cur.nnz > 0 ? cur.nnz : 1));
+        if (!Srp || !Sci) st = OR_E_NOMEM;
+        else {
+            memcpy(Srp, cur.rp, sizeof(int32_t) * (size_t)(n + 1));
+            memcpy(Sci, cur.ci, sizeof(int32_t) * (size_t)cur.nnz);
+        }
+    }
+    /* Alg. 2 steps 2-5 / Alg. 3 steps 5-8: m passes with dropping */
+    for (int k = 0; k < m && st == OR_OK; k++) {
+        or_builder nxt;
+        st = bld_init(&nxt, n, cur.nnz + n);
+        if (st == OR_OK) st = sait_pass(n, Trp, Tci, Tv, w.dinv, cur.rp, cur.ci, cur.v, tau, cap,
+                                        Srp, Sci, w.acc, w.touched, w.list, w.inS, w.ent, &nxt);
+        bld_free(&cur);
+        cur = nxt;
+    }
+    /* final step: M = M D^-1  (column j scaled by fl(1/d_j)) */
+    if (st == OR_OK) {
+        for (int64_t q = 0; q < cur.nnz; q++) cur.v[q] = cur.v[q] * w.dinv[cur.ci[q]];
+        bld_give(&cur, Orp, Oci, Ov);
+    } else {
+        bld_free(&cur);
+    }
+    free(Srp); free(Sci);
+    ws_free(&w);
+    return st;
+}
+
+/* SAIT_Thr(tau, m) with optional per-row cap (Alg. 2; Appendix A). */
+int or_sait_thr(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
+                double tau, int m, int cap,
+                int32_t **Orp, int32_t **Oci, double **Ov) {
+    if (!(tau >= 0.0 && tau < 1.0) || m < 0 || cap < 0) return OR_E_INVALID;
+    return sait_run(n, Trp, Tci, Tv, tau, m, cap, -1, Orp, Oci, Ov);
+}
+
+/* SAIT_Pat(p, m) (Alg. 3): p passes without dropping fix the pattern S of
+ * T^p (= pattern of M_{p+1} in Eq. M_poly), m further passes masked to S. */
+int or_sait_pat(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
+                int p, int m,
+                int32_t **Orp, int32_t **Oci, double **Ov) {
+    if (p < 0 || m < 0) return OR_E_INVALID;
+    return sait_run(n, Trp, Tci, Tv, 0.0, m, 0, p, Orp, Oci, Ov);
+}
+
+/* ------------------------------------------------------------------ */
+/* Apply (Sec. 3.1: U(Lx) = y replaced by x = M_U (M_L y))              */
+/* ------------------------------------------------------------------ */
+
+void or_spmv(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+             const double *x, double *y) {
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) s = s + v[p] * x[ci[p]];
+        y[i] = s;
+    }
+}
+
+/* z = second * (first * r): (first, second) = (M_L, M_U) for the
+ * preconditioner, (M_U^T, M_L^T) for its transpose. */
+int or_apply(int64_t n,
+             const int32_t *Arp, const int32_t *Aci, const double *Av,
+             const int32_t *Brp, const int32_t *Bci, const double *Bv,
+             const double *r, double *z) {
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!y) return OR_E_NOMEM;
+    or_spmv(n, Arp, Aci, Av, r, y);
+    or_spmv(n, Brp, Bci, Bv, y, z);
+    free(y);
+    return OR_OK;
+}
+
+/* Storage roundings of the factor values: binary32 by round-to-nearest-
+ * even, and bfloat16 as the round-to-nearest-even of that binary32 value
+ * (upper 16 bits of the binary32 encoding). */
+void or_round_f32(int64_t n, const double *in, float *out) {
+    for (int64_t i = 0; i < n; i++) out[i] = (float)in[i];
+}
+
+static uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u); /* quiet NaN */
+    uint32_t lsb = (u >> 16) & 1u;
+    u = u + 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+void or_round_bf16(int64_t n, const double *in, uint16_t *out) {
+    for (int64_t i = 0; i < n; i++) out[i] = f32_to_bf16_rne((float)in[i]);
+}
+
+void or_bf16_to_f32(int64_t n, const uint16_t *in, float *out) {
+    for (int64_t i = 0; i < n; i++) {
+        uint32_t u = ((uint32_t)in[i]) << 16;
+        memcpy(&out[i], &u, 4);
+    }
+}
+
+/* Mixed apply with binary32 accumulation: r32 = fl32(r), y32 = A32 r32,
+ * z = (double)(B32 y32), each row summed in column order in binary32. */
+int or_apply_f32acc(int64_t n,
+                    const int32_t *Arp, const int32_t *Aci, const float *Av,
+                    const int32_t *Brp, const int32_t *Bci, const float *Bv,
+                    const double *r, double *z) {
+    float *r32 = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    float *y32 = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    if (!r32 || !y32) { free(r32); free(y32); return OR_E_NOMEM; }
+    for (int64_t i = 0; i < n; i++) r32[i] = (float)r[i];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        float s = 0.0f;
+        for (int64_t p = Arp[i]; p < Arp[i + 1]; p++) s = s + Av[p] * r32[Aci[p]];
+        y32[i] = s;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        float s = 0.0f;
+        for (int64_t p = Brp[i]; p < Brp[i + 1]; p++) s = s + Bv[p] * y32[Bci[p]];
+        z[i] = (double)s;
+    }
+    free(r32); free(y32);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Transpose and the adjoint gradient                                   */
+/* ------------------------------------------------------------------ */
+int or_transpose(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                 int32_t **Orp, int32_t **Oci, double **Ov) {
+    int64_t nnz = rp[n];
+    int32_t *orp = (int32_t *)calloc((size_t)(n + 1), sizeof(int32_t));
+    int32_t *oci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double *ov = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!orp || !oci || !ov || !fill) { free(orp); free(oci); free(ov); free(fill); return OR_E_NOMEM; }
+    for (int64_t p = 0; p < nnz; p++) orp[ci[p] + 1]++;
+    for (int64_t j = 0; j < n; j++) orp[j + 1] += orp[j];
+    for (int64_t j = 0; j < n; j++) fill[j] = orp[j];
+    for (int64_t i = 0; i < n; i++)         /* rows in increasing order: output rows sorted */
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            int32_t j = ci[p];
+            oci[fill[j]] = (int32_t)i;
+            ov[fill[j]] = v[p];
+            fill[j]++;
+        }
+    free(fill);
+    *Orp = orp; *Oci = oci; *Ov = ov;
+    return OR_OK;
+}
+
+/* Gradient of a loss through x = A^-1 b with respect to the stored
+ * entries of A, given the adjoint lambda = A^-T dloss/dx:
+ * dloss/dA_ij = -lambda_i x_j on the pattern of A. */
+void or_grad_values(int64_t n, const int32_t *rp, const int32_t *ci,
+                    const double *lambda, const double *x, double *grad) {
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) grad[p] = -(lambda[i] * x[ci[p]]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Restarted GMRES / FGMRES, right preconditioned                       */
+/* ------------------------------------------------------------------ */
+
+/* Preconditioner kinds. */
+#define OR_PREC_NONE 0
+#define OR_PREC_SAIT64 1   /* z = M2 (M1 r), FP64 values */
+#define OR_PREC_SAIT32 2   /* z = (double)(M2_32 (M1_32 fl32(r))), binary32 */
+#define OR_PREC_EXACT 3    /* z = U^-1 (L^-1 r): M1 = L (lower), M2 = U (upper) */
+
+typedef struct {
+    int kind;
+    const int32_t *rp1, *ci1;
+    const double *v1;
+    const float *f1;
+    const int32_t *rp2, *ci2;
+    const double *v2;
+    const float *f2;
+} or_prec;
+
+static int prec_apply(int64_t n, const or_prec *P, const double *r, double *z, double *tmp) {
+    switch (P ? P->kind : OR_PREC_NONE) {
+    case OR_PREC_NONE:
+        memcpy(z, r, sizeof(double) * (size_t)n);
+        return OR_OK;
+    case OR_PREC_SAIT64:
+        or_spmv(n, P->rp1, P->ci1, P->v1, r, tmp);
+        or_spmv(n, P->rp2, P->ci2, P->v2, tmp, z);
+        return OR_OK;
+    case OR_PREC_SAIT32:
+        return or_apply_f32acc(n, P->rp1, P->ci1, P->f1, P->rp2, P->ci2, P->f2, r, z);
+    case OR_PREC_EXACT: {
+        int st = or_lower_solve(n, P->rp1, P->ci1, P->v1, r, tmp);
+        if (st) return st;
+        return or_upper_solve(n, P->rp2, P->ci2, P->v2, tmp, z);
+    }
+    default:
+        return OR_E_INVALID;
+    }
+}
+
+static double dot(int64_t n, const double *a, const double *b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s = s + a[i] * b[i];
+    return s;
+}
+
+/*
+ * x (in: x0, out: solution).  Stops on the true relative residual
+ * ||b - A x|| / ||b|| <= rtol checked at the end of every cycle; a cycle
+ * ends after `restart` inner steps, when the Arnoldi residual estimate
+ * |g_{j+1}| / ||b|| <= rtol, on breakdown (h_{j+1,j} == 0) or at maxit.
+ * iters = total inner steps.  hist (may be NULL, length maxit) receives
+ * the estimate after every inner step.
+ */
+int or_gmres(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+             const or_prec *P, const double *b, double *x,
+             int restart, int maxit, double rtol, int flexible,
+             int *iters_out, int *restarts_out, double *relres_out, double *est_out, double *hist) {
+    if (restart < 1 || maxit < 0 || !(rtol >= 0.0)) return OR_E_INVALID;
+    int k = restart;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *V = (double *)malloc(sizeof(double) * nn * (size_t)(k + 1));
+    double *Z = flexible ? (double *)malloc(sizeof(double) * nn * (size_t)k) : NULL;
+    double *H = (double *)calloc((size_t)(k + 1) * (size_t)k, sizeof(double)); /* H[i*k + j] */
+    double *cs = (double *)malloc(sizeof(double) * (size_t)k);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)k);
+    double *g = (double *)malloc(sizeof(double) * (size_t)(k + 1));
+    double *y = (double *)malloc(sizeof(double) * (size_t)k);
+    double *r = (double *)malloc(sizeof(double) * nn);
+    double *w = (double *)malloc(sizeof(double) * nn);
+    double *z = (double *)malloc(sizeof(double) * nn);
+    double *tmp = (double *)malloc(sizeof(double) * nn);
+    int st = OR_OK;
+    if (!V || (flexible && !Z) || !H || !cs || !sn || !g || !y || !r || !w || !z || !tmp) st = OR_E_NOMEM;
+    double nb = st == OR_OK ? sqrt(dot(n, b, b)) : 0.0;
+    int iters = 0, restarts = 0;
+    double relres = 0.0, est = 0.0;
+    if (st == OR_OK && nb == 0.0) {
+        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+    } else if (st == OR_OK) {
+        for (;;) {
+            or_spmv(n, rp, ci, v, x, r);
+            for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+            double beta = sqrt(dot(n, r, r));
+            relres = beta / nb;
+            if (relres <= rtol) { st = OR_OK; break; }
+            if (iters >= maxit) { st = OR_NOT_CONVERGED; break; }
+            for (int64_t i = 0; i < n; i++) V[i] = r[i] / beta;
+            for (int i = 0; i <= k; i++) g[i] = 0.0;
+            g[0] = beta;
+            int jend = 0;
+            for (int j = 0; j < k; j++) {
+                double *vj = V + (size_t)j * nn;
+                double *zj = flexible ? Z + (size_t)j * nn : z;
+                st = prec_apply(n, P, vj, zj, tmp);
+                if (st) break;
+                or_spmv(n, rp, ci, v, zj, w);
+                for (int i = 0; i <= j; i++) {            /* modified Gram-Schmidt */
+                    double *vi = V + (size_t)i * nn;
+                    double h = dot(n, w, vi);
+                    H[i * k + j] = h;
+                    for (int64_t t = 0; t < n; t++) w[t] = w[t] - h * vi[t];
+                }
+                double hn = sqrt(dot(n, w, w));
+                H[(j + 1) * k + j] = hn;
+                for (int i = 0; i < j; i++) {              /* previous rotations */
+                    double a = H[i * k + j], c = H[(i + 1) * k + j];
+                    H[i * k + j] = cs[i] * a + sn[i] * c;
+                    H[(i + 1) * k + j] = -sn[i] * a + cs[i] * c;
+                }
+                double a = H[j * k + j], c = H[(j + 1) * k + j];
+                double den = hypot(a, c);
+                if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+                else { cs[j] = a / den; sn[j] = c / den; }
+                H[j * k + j] = den;
+                H[(j + 1) * k + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                iters++;
+                jend = j + 1;
+                est = fabs(g[j + 1]) / nb;
+                if (hist && iters <= maxit) hist[iters - 1] = est;
+                if (hn == 0.0) break;                      /* lucky breakdown */
+                double *vn = V + (size_t)(j + 1) * nn;
+                for (int64_t t = 0; t < n; t++) vn[t] = w[t] / hn;
+                if (est <= rtol || iters >= maxit) break;
+            }
+            if (st) break;
+            /* y = R^-1 g (upper triangular back substitution) */
+            for (int i = jend - 1; i >= 0; i--) {
+                double s = g[i];
+                for (int t = i + 1; t < jend; t++) s = s - H[i * k + t] * y[t];
+                y[i] = H[i * k + i] != 0.0 ? s / H[i * k + i] : 0.0;
+            }
+            if (flexible) {
+                for (int i = 0; i < jend; i++) {
+                    double *zi = Z + (size_t)i * nn;
+                    for (int64_t t = 0; t < n; t++) x[t] = x[t] + y[i] * zi[t];
+                }
+            } else {
+                for (int64_t t = 0; t < n; t++) w[t] = 0.0;
+                for (int i = 0; i < jend; i++) {
+                    double *vi = V + (size_t)i * nn;
+                    for (int64_t t = 0; t < n; t++) w[t] = w[t] + y[i] * vi[t];
+                }
+                st = prec_apply(n, P, w, z, tmp);
+                if (st) break;
+                for (int64_t t = 0; t < n; t++) x[t] = x[t] + z[t];
+            }
+            restarts++;
+        }
+    }
+    if (iters_out) *iters_out = iters;
+    if (restarts_out) *restarts_out = restarts;
+    if (relres_out) *relres_out = relres;
+    if (est_out) *est_out = est;
+    free(V); free(Z); free(H); free(cs); free(sn); free(g); free(y); free(r); free(w); free(z); free(tmp);
+    return st;
+}
