@@ -1,0 +1,533 @@
+// extern "C" entry points of libsait (declared in include/sait.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+
+#include "sait_internal.h"
+#include "solver.h"
+
+namespace sait {
+
+namespace {
+thread_local std::string g_last_error;
+
+int set_error(int status, const std::string &msg) {
+    g_last_error = msg;
+    return status;
+}
+
+void *default_alloc(size_t bytes) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+}  // namespace
+
+[[noreturn]] void fail(int status, const std::string &msg) { throw Error(status, msg); }
+
+void *Allocator::alloc(size_t bytes) {
+    void *p = has_user ? user.alloc(bytes, user.ctx) : default_alloc(bytes);
+    if (!p) {
+        (void)hipGetLastError();  // clear a sticky out-of-memory error
+        fail(SAIT_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+void Allocator::release(void *p) {
+    if (!p) return;
+    if (has_user) user.free(p, user.ctx);
+    else (void)hipFree(p);
+}
+
+void DevBuf::alloc(Allocator *a, size_t bytes) {
+    reset();
+    a_ = a;
+    bytes_ = std::max<size_t>(bytes, 64);
+    p_ = a->alloc(bytes_);
+}
+
+void DevBuf::reset() {
+    if (p_ && a_) a_->release(p_);
+    p_ = nullptr;
+    bytes_ = 0;
+}
+
+}  // namespace sait
+
+using namespace sait;
+
+struct sait_handle_s {
+    Allocator alloc;
+    int device = 0;
+    int64_t n = 0;
+    int nsys = 1;
+    std::vector<int64_t> sys_ptr;
+    sait_build_opts opts{};
+    HostCsr A_h, L_h, U_h;
+    DevCsr A, ML, MU, At, MLt, MUt;
+    bool has_transpose = false;
+    int lanesA = 8, lanesL = 8, lanesU = 8, lanesAt = 8, lanesLt = 8, lanesUt = 8;
+    DevBuf tmp;     // apply intermediate
+    DevBuf At_perm; // At.v[q] = A.v[At_perm[q]]
+    Solver solver;
+};
+
+namespace {
+
+template <class F> int guard(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        return set_error(e.status, e.what());
+    } catch (const std::bad_alloc &) {
+        return set_error(SAIT_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return set_error(SAIT_E_INVALID, e.what());
+    }
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+void check_handle(sait_handle h) {
+    if (!h) fail(SAIT_E_INVALID, "null handle");
+    int dev = -1;
+    SAIT_HIP(hipGetDevice(&dev));
+    if (dev != h->device) fail(SAIT_E_INVALID, "handle belongs to another device than the current one");
+}
+
+void check_block(int64_t n, int nrhs, int64_t ld, const void *p, const char *what) {
+    if (nrhs < 1) fail(SAIT_E_INVALID, "nrhs must be >= 1");
+    if (ld < nrhs) fail(SAIT_E_INVALID, "leading dimension must be >= nrhs");
+    if (n > 0 && !p) fail(SAIT_E_INVALID, std::string("null device pointer: ") + what);
+}
+
+void ensure_tmp(sait_handle h, int64_t elems, size_t esize) {
+    const size_t need = (size_t)std::max<int64_t>(elems, 1) * esize;
+    if (h->tmp.bytes() < need) h->tmp.alloc(&h->alloc, need);
+}
+
+void apply_impl(sait_handle h, const double *r, double *z, int nrhs, int64_t ld, int transpose, hipStream_t s) {
+    const DevCsr *M1 = transpose ? &h->MUt : &h->ML;
+    const DevCsr *M2 = transpose ? &h->MLt : &h->MU;
+    const int l1 = transpose ? h->lanesUt : h->lanesL;
+    const int l2 = transpose ? h->lanesLt : h->lanesU;
+    const int64_t n = h->n;
+    if (h->opts.precision == SAIT_F64) {
+        ensure_tmp(h, n * nrhs, sizeof(double));
+        spmv(*M1, r, XKind::F64, h->tmp.as<void>(), YKind::F64, nrhs, ld, nrhs, l1, s);
+        spmv(*M2, h->tmp.as<void>(), XKind::F64, z, YKind::F64, nrhs, nrhs, ld, l2, s);
+    } else {
+        ensure_tmp(h, n * nrhs, sizeof(float));
+        spmv(*M1, r, XKind::F64, h->tmp.as<void>(), YKind::F32, nrhs, ld, nrhs, l1, s);
+        spmv(*M2, h->tmp.as<void>(), XKind::F32, z, YKind::F64, nrhs, nrhs, ld, l2, s);
+    }
+}
+
+const DevCsr *factor_of(sait_handle h, int which) {
+    switch (which) {
+    case SAIT_MAT_ML: return &h->ML;
+    case SAIT_MAT_MU: return &h->MU;
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void sait_default_build_opts(sait_build_opts *o) {
+    if (!o) return;
+    o->ilu_kind = SAIT_ILU0;
+    o->ilut_tau = 1e-3;
+    o->ilut_fill = 10;
+    o->m = 3;
+    o->tau = 1e-2;
+    o->max_nnz_row = 0;
+    o->pattern_p = -1;
+    o->precision = SAIT_F64;
+    o->build_transpose = 0;
+}
+
+void sait_default_solve_opts(sait_solve_opts *o) {
+    if (!o) return;
+    o->restart = 30;
+    o->maxit = 10000;
+    o->rtol = 1e-8;
+    o->flexible = 0;
+}
+
+const char *sait_last_error(void) { return g_last_error.c_str(); }
+
+int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val, int nsys,
+               const int64_t *sys_ptr, const sait_build_opts *o, const sait_allocator *a, void *hip_stream,
+               sait_handle *out) {
+    return guard([&]() -> int {
+        if (!out) fail(SAIT_E_INVALID, "null output handle pointer");
+        *out = nullptr;
+        sait_build_opts opts;
+        sait_default_build_opts(&opts);
+        if (o) opts = *o;
+        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT) fail(SAIT_E_INVALID, "unknown ilu_kind");
+        if (opts.precision != SAIT_F64 && opts.precision != SAIT_F32 && opts.precision != SAIT_BF16)
+            fail(SAIT_E_INVALID, "unknown precision");
+        if (!(opts.tau >= 0.0 && opts.tau < 1.0)) fail(SAIT_E_INVALID, "tau must satisfy 0 <= tau < 1");
+        if (opts.m < 0) fail(SAIT_E_INVALID, "m must be >= 0");
+        if (opts.max_nnz_row < 0) fail(SAIT_E_INVALID, "max_nnz_row must be >= 0");
+        if (nsys < 1) fail(SAIT_E_INVALID, "nsys must be >= 1");
+        if (a && (!a->alloc || !a->free)) fail(SAIT_E_INVALID, "allocator needs both alloc and free");
+        validate_csr(n, row_ptr, col_idx, val, "A");
+        if (row_ptr[n] > 0 && !val) fail(SAIT_E_INVALID, "null values of A");
+        std::unique_ptr<sait_handle_s> h(new sait_handle_s());
+        if (a) {
+            h->alloc.user = *a;
+            h->alloc.has_user = true;
+        }
+        SAIT_HIP(hipGetDevice(&h->device));
+        h->n = n;
+        h->nsys = nsys;
+        h->opts = opts;
+        if (nsys > 1 || sys_ptr) {
+            if (!sys_ptr) fail(SAIT_E_INVALID, "nsys > 1 needs sys_ptr");
+            if (sys_ptr[0] != 0 || sys_ptr[nsys] != n) fail(SAIT_E_INVALID, "sys_ptr must run from 0 to n");
+            for (int k = 0; k < nsys; ++k)
+                if (sys_ptr[k + 1] <= sys_ptr[k]) fail(SAIT_E_INVALID, "sys_ptr must be strictly increasing");
+            h->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
+            int k = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                while (i >= sys_ptr[k + 1]) ++k;
+                for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+                    if (col_idx[p] < sys_ptr[k] || col_idx[p] >= sys_ptr[k + 1])
+                        fail(SAIT_E_INVALID, "an entry of A couples two systems");
+            }
+        } else {
+            h->sys_ptr = {0, n};
+        }
+        h->A_h.n = n;
+        h->A_h.rp.assign(row_ptr, row_ptr + n + 1);
+        h->A_h.ci.assign(col_idx, col_idx + row_ptr[n]);
+        h->A_h.v.assign(val, val + row_ptr[n]);
+        if (opts.ilu_kind == SAIT_ILU0) host_ilu0(h->A_h, h->L_h, h->U_h);
+        else host_ilut(h->A_h, opts.ilut_tau, opts.ilut_fill, h->L_h, h->U_h);
+
+        hipStream_t s = as_stream(hip_stream);
+        upload_csr(&h->alloc, h->A_h, h->A, s);
+        SaitParams p;
+        p.m = opts.m;
+        p.tau = opts.tau;
+        p.cap = opts.max_nnz_row;
+        p.pattern_p = opts.pattern_p;
+        p.precision = opts.precision;
+        {
+            DevCsr T;
+            upload_csr(&h->alloc, h->L_h, T, s);
+            build_sait_factor(&h->alloc, T, p, h->ML, s);
+        }
+        {
+            DevCsr T;
+            upload_csr(&h->alloc, h->U_h, T, s);
+            build_sait_factor(&h->alloc, T, p, h->MU, s);
+        }
+        if (opts.build_transpose) {
+            transpose_csr(&h->alloc, h->A, h->At, s);
+            transpose_perm(&h->alloc, h->A, h->At_perm, s);
+            transpose_csr(&h->alloc, h->ML, h->MLt, s);
+            transpose_csr(&h->alloc, h->MU, h->MUt, s);
+            cast_values(&h->alloc, h->MLt, opts.precision, s);
+            cast_values(&h->alloc, h->MUt, opts.precision, s);
+            h->has_transpose = true;
+            h->lanesAt = default_lanes(h->At);
+            h->lanesLt = default_lanes(h->MLt);
+            h->lanesUt = default_lanes(h->MUt);
+        }
+        h->lanesA = default_lanes(h->A);
+        h->lanesL = default_lanes(h->ML);
+        h->lanesU = default_lanes(h->MU);
+        SAIT_HIP(hipStreamSynchronize(s));
+        *out = h.release();
+        return SAIT_OK;
+    });
+}
+
+int sait_apply(sait_handle h, const double *r, double *z, int nrhs, int64_t ld, int transpose, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        check_block(h->n, nrhs, ld, r, "r");
+        check_block(h->n, nrhs, ld, z, "z");
+        if (transpose && !h->has_transpose) fail(SAIT_E_INVALID, "transpose apply needs build_transpose");
+        if (h->n > 0 && r == z) fail(SAIT_E_INVALID, "r and z must not overlap");
+        apply_impl(h, r, z, nrhs, ld, transpose, as_stream(hip_stream));
+        return SAIT_OK;
+    });
+}
+
+int sait_matvec(sait_handle h, const double *x, double *y, int nrhs, int64_t ld, int transpose, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        check_block(h->n, nrhs, ld, x, "x");
+        check_block(h->n, nrhs, ld, y, "y");
+        if (transpose && !h->has_transpose) fail(SAIT_E_INVALID, "transpose product needs build_transpose");
+        if (h->n > 0 && x == y) fail(SAIT_E_INVALID, "x and y must not overlap");
+        const DevCsr &A = transpose ? h->At : h->A;
+        spmv(A, x, XKind::F64, y, YKind::F64, nrhs, ld, ld, transpose ? h->lanesAt : h->lanesA, as_stream(hip_stream));
+        return SAIT_OK;
+    });
+}
+
+int sait_solve(sait_handle h, const double *b, double *x, int nrhs, int64_t ld, int transpose,
+               const sait_solve_opts *o, sait_solve_info *info, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        check_block(h->n, nrhs, ld, b, "b");
+        check_block(h->n, nrhs, ld, x, "x");
+        if (transpose && !h->has_transpose) fail(SAIT_E_INVALID, "transpose solve needs build_transpose");
+        if (h->n > 0 && b == x) fail(SAIT_E_INVALID, "b and x must not overlap");
+        sait_solve_opts opts;
+        sait_default_solve_opts(&opts);
+        if (o) opts = *o;
+        if (h->nsys != 1 || nrhs != 1 || ld != 1)
+            fail(SAIT_E_INVALID, "batched solves (nsys > 1 or nrhs > 1) are not available in this build");
+        Ops ops;
+        ops.A = transpose ? &h->At : &h->A;
+        ops.M1 = transpose ? &h->MUt : &h->ML;
+        ops.M2 = transpose ? &h->MLt : &h->MU;
+        ops.lanesA = transpose ? h->lanesAt : h->lanesA;
+        ops.lanes1 = transpose ? h->lanesUt : h->lanesL;
+        ops.lanes2 = transpose ? h->lanesLt : h->lanesU;
+        ops.precision = h->opts.precision;
+        return h->solver.solve(&h->alloc, ops, b, x, opts, info, as_stream(hip_stream));
+    });
+}
+
+int sait_set_values(sait_handle h, const double *val, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        if (h->A.nnz > 0 && !val) fail(SAIT_E_INVALID, "null values");
+        hipStream_t s = as_stream(hip_stream);
+        if (h->A.nnz)
+            SAIT_HIP(hipMemcpyAsync(h->A.v.as<void>(), val, (size_t)h->A.nnz * sizeof(double),
+                                    hipMemcpyDeviceToDevice, s));
+        if (h->has_transpose) gather_values(h->At.nnz, h->At_perm.as<int>(), h->A.v.as<double>(), h->At.v.as<double>(), s);
+        return SAIT_OK;
+    });
+}
+
+int sait_grad_values(sait_handle h, const double *lambda, const double *x, double *grad_val, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        if (h->n > 0 && (!lambda || !x)) fail(SAIT_E_INVALID, "null lambda or x");
+        if (h->A.nnz > 0 && !grad_val) fail(SAIT_E_INVALID, "null grad_val");
+        grad_values(h->A, lambda, x, grad_val, as_stream(hip_stream));
+        return SAIT_OK;
+    });
+}
+
+int sait_query(sait_handle h, int64_t *n, int64_t *nnz_A, int64_t *nnz_L, int64_t *nnz_U, int64_t *nnz_ML,
+               int64_t *nnz_MU) {
+    return guard([&]() -> int {
+        if (!h) fail(SAIT_E_INVALID, "null handle");
+        if (n) *n = h->n;
+        if (nnz_A) *nnz_A = h->A_h.nnz();
+        if (nnz_L) *nnz_L = h->L_h.nnz();
+        if (nnz_U) *nnz_U = h->U_h.nnz();
+        if (nnz_ML) *nnz_ML = h->ML.nnz;
+        if (nnz_MU) *nnz_MU = h->MU.nnz;
+        return SAIT_OK;
+    });
+}
+
+int sait_export(sait_handle h, int which, int32_t *row_ptr, int32_t *col_idx, double *val, void *stored) {
+    return guard([&]() -> int {
+        check_handle(h);
+        const HostCsr *hc = nullptr;
+        HostCsr tmp;
+        const DevCsr *dc = factor_of(h, which);
+        switch (which) {
+        case SAIT_MAT_A: hc = &h->A_h; break;
+        case SAIT_MAT_L: hc = &h->L_h; break;
+        case SAIT_MAT_U: hc = &h->U_h; break;
+        case SAIT_MAT_ML:
+        case SAIT_MAT_MU:
+            download_csr(*dc, tmp, nullptr);
+            hc = &tmp;
+            break;
+        default: fail(SAIT_E_INVALID, "unknown matrix id");
+        }
+        if (row_ptr) std::copy(hc->rp.begin(), hc->rp.end(), row_ptr);
+        if (col_idx) std::copy(hc->ci.begin(), hc->ci.end(), col_idx);
+        if (val) std::copy(hc->v.begin(), hc->v.end(), val);
+        if (stored) {
+            if (!dc) fail(SAIT_E_INVALID, "stored values exist only for M_L and M_U");
+            const size_t es = dc->precision == SAIT_F64 ? 8 : dc->precision == SAIT_F32 ? 4 : 2;
+            if (dc->nnz) SAIT_HIP(hipMemcpy(stored, dc->stored(), (size_t)dc->nnz * es, hipMemcpyDeviceToHost));
+        }
+        return SAIT_OK;
+    });
+}
+
+void sait_destroy(sait_handle h) {
+    if (!h) return;
+    try {
+        int dev = -1;
+        const int hdev = h->device;
+        (void)hipGetDevice(&dev);
+        if (dev != hdev) (void)hipSetDevice(hdev);
+        (void)hipDeviceSynchronize();
+        delete h;
+        if (dev >= 0 && dev != hdev) (void)hipSetDevice(dev);
+    } catch (...) {
+    }
+}
+
+int sait_set_apply_lanes(sait_handle h, int lanes_L, int lanes_U) {
+    return guard([&]() -> int {
+        if (!h) fail(SAIT_E_INVALID, "null handle");
+        auto ok = [](int l) { return l == 0 || (l >= 1 && l <= 64 && (l & (l - 1)) == 0); };
+        if (!ok(lanes_L) || !ok(lanes_U)) fail(SAIT_E_INVALID, "lanes must be 0 or a power of two in 1..64");
+        if (lanes_L) h->lanesL = lanes_L;
+        if (lanes_U) h->lanesU = lanes_U;
+        return SAIT_OK;
+    });
+}
+
+int sait_get_apply_lanes(sait_handle h, int *lanes_L, int *lanes_U) {
+    return guard([&]() -> int {
+        if (!h) fail(SAIT_E_INVALID, "null handle");
+        if (lanes_L) *lanes_L = h->lanesL;
+        if (lanes_U) *lanes_U = h->lanesU;
+        return SAIT_OK;
+    });
+}
+
+int sait_autotune(sait_handle h, int nrhs, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        if (nrhs < 1) fail(SAIT_E_INVALID, "nrhs must be >= 1");
+        hipStream_t s = as_stream(hip_stream);
+        const int64_t n = h->n;
+        if (n == 0) return SAIT_OK;
+        DevBuf x, y;
+        x.alloc(&h->alloc, (size_t)n * nrhs * sizeof(double));
+        y.alloc(&h->alloc, (size_t)n * nrhs * sizeof(double));
+        SAIT_HIP(hipMemsetAsync(x.as<void>(), 0, (size_t)n * nrhs * sizeof(double), s));
+        hipEvent_t e0, e1;
+        SAIT_HIP(hipEventCreate(&e0));
+        SAIT_HIP(hipEventCreate(&e1));
+        const bool mixed = h->opts.precision != SAIT_F64;
+        auto best_for = [&](const DevCsr &M, XKind xk, YKind yk) {
+            int best = default_lanes(M);
+            float best_ms = 1e30f;
+            for (int l = 1; l <= 64; l <<= 1) {
+                spmv(M, x.as<void>(), xk, y.as<void>(), yk, nrhs, nrhs, nrhs, l, s);  // warm-up
+                SAIT_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 5; ++r) spmv(M, x.as<void>(), xk, y.as<void>(), yk, nrhs, nrhs, nrhs, l, s);
+                SAIT_HIP(hipEventRecord(e1, s));
+                SAIT_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                SAIT_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = l;
+                }
+            }
+            return best;
+        };
+        h->lanesL = best_for(h->ML, XKind::F64, mixed ? YKind::F32 : YKind::F64);
+        h->lanesU = best_for(h->MU, mixed ? XKind::F32 : XKind::F64, YKind::F64);
+        h->lanesA = best_for(h->A, XKind::F64, YKind::F64);
+        if (h->has_transpose) {
+            h->lanesUt = best_for(h->MUt, XKind::F64, mixed ? YKind::F32 : YKind::F64);
+            h->lanesLt = best_for(h->MLt, mixed ? XKind::F32 : XKind::F64, YKind::F64);
+            h->lanesAt = best_for(h->At, XKind::F64, YKind::F64);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return SAIT_OK;
+    });
+}
+
+int sait_time_apply(sait_handle h, const double *r, double *z, int reps, void *hip_stream, double *ms_L,
+                    double *ms_U, double *ms_apply) {
+    return guard([&]() -> int {
+        check_handle(h);
+        if (reps < 1) fail(SAIT_E_INVALID, "reps must be >= 1");
+        check_block(h->n, 1, 1, r, "r");
+        check_block(h->n, 1, 1, z, "z");
+        hipStream_t s = as_stream(hip_stream);
+        const bool mixed = h->opts.precision != SAIT_F64;
+        ensure_tmp(h, h->n, sizeof(double));
+        std::vector<hipEvent_t> ev(3 * reps);
+        for (auto &e : ev) SAIT_HIP(hipEventCreate(&e));
+        for (int k = 0; k < reps; ++k) {
+            SAIT_HIP(hipEventRecord(ev[3 * k], s));
+            spmv(h->ML, r, XKind::F64, h->tmp.as<void>(), mixed ? YKind::F32 : YKind::F64, 1, 1, 1, h->lanesL, s);
+            SAIT_HIP(hipEventRecord(ev[3 * k + 1], s));
+            spmv(h->MU, h->tmp.as<void>(), mixed ? XKind::F32 : XKind::F64, z, YKind::F64, 1, 1, 1, h->lanesU, s);
+            SAIT_HIP(hipEventRecord(ev[3 * k + 2], s));
+        }
+        SAIT_HIP(hipEventSynchronize(ev[3 * reps - 1]));
+        double sl = 0, su = 0, sa = 0;
+        for (int k = 0; k < reps; ++k) {
+            float a = 0, b = 0;
+            SAIT_HIP(hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]));
+            SAIT_HIP(hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]));
+            sl += a;
+            su += b;
+            sa += a + b;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        if (ms_L) *ms_L = sl / reps;
+        if (ms_U) *ms_U = su / reps;
+        if (ms_apply) *ms_apply = sa / reps;
+        return SAIT_OK;
+    });
+}
+
+int sait_debug_step(int64_t n, const int32_t *T_row_ptr, const int32_t *T_col_idx, const double *T_val,
+                    const int32_t *M_row_ptr, const int32_t *M_col_idx, const double *M_val, double tau,
+                    int max_nnz_row, int64_t capacity, int32_t *out_row_ptr, int32_t *out_col_idx, double *out_val,
+                    int64_t *out_nnz) {
+    return guard([&]() -> int {
+        validate_csr(n, T_row_ptr, T_col_idx, T_val, "T");
+        validate_csr(n, M_row_ptr, M_col_idx, M_val, "M");
+        if (!out_row_ptr || !out_nnz) fail(SAIT_E_INVALID, "null output");
+        // T must be triangular (either orientation) with its diagonal present
+        bool lower = true, upper = true;
+        for (int64_t i = 0; i < n; ++i) {
+            bool diag = false;
+            for (int64_t p = T_row_ptr[i]; p < T_row_ptr[i + 1]; ++p) {
+                if (T_col_idx[p] > i) lower = false;
+                if (T_col_idx[p] < i) upper = false;
+                if (T_col_idx[p] == i) diag = T_val[p] != 0.0;
+            }
+            if (!diag) fail(SAIT_E_ZERO_PIVOT, "T has a zero or missing diagonal entry in row " + std::to_string(i));
+        }
+        if (!lower && !upper) fail(SAIT_E_INVALID, "T must be triangular");
+        Allocator a;
+        HostCsr Th, Mh, Oh;
+        Th.n = Mh.n = n;
+        Th.rp.assign(T_row_ptr, T_row_ptr + n + 1);
+        Th.ci.assign(T_col_idx, T_col_idx + T_row_ptr[n]);
+        Th.v.assign(T_val, T_val + T_row_ptr[n]);
+        Mh.rp.assign(M_row_ptr, M_row_ptr + n + 1);
+        Mh.ci.assign(M_col_idx, M_col_idx + M_row_ptr[n]);
+        Mh.v.assign(M_val, M_val + M_row_ptr[n]);
+        DevCsr T, M, O;
+        upload_csr(&a, Th, T, nullptr);
+        upload_csr(&a, Mh, M, nullptr);
+        sait_single_pass(&a, T, M, tau, max_nnz_row, O, nullptr);
+        download_csr(O, Oh, nullptr);
+        *out_nnz = Oh.nnz();
+        std::copy(Oh.rp.begin(), Oh.rp.end(), out_row_ptr);
+        if (Oh.nnz() > capacity) fail(SAIT_E_INVALID, "output capacity too small");
+        if (Oh.nnz() && (!out_col_idx || !out_val)) fail(SAIT_E_INVALID, "null output arrays");
+        std::copy(Oh.ci.begin(), Oh.ci.end(), out_col_idx);
+        std::copy(Oh.v.begin(), Oh.v.end(), out_val);
+        return SAIT_OK;
+    });
+}
+
+}  // extern "C"

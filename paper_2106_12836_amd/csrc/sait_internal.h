@@ -1,0 +1,150 @@
+// Internal declarations of libsait (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sait.h"
+
+namespace sait {
+
+// ---------------------------------------------------------------------------
+// Error model: everything below the C ABI throws sait::Error; the extern "C"
+// wrappers catch it, store the message thread-locally and return the status.
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    int status;
+    Error(int st, const std::string &msg) : std::runtime_error(msg), status(st) {}
+};
+
+[[noreturn]] void fail(int status, const std::string &msg);
+
+#define SAIT_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::sait::fail(e_ == hipErrorOutOfMemory ? SAIT_E_NOMEM : SAIT_E_DEVICE,      \
+                         std::string(#call) + ": " + hipGetErrorString(e_));            \
+    } while (0)
+
+#define SAIT_LAUNCH_CHECK() SAIT_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Device memory owned through the handle's allocator.
+// ---------------------------------------------------------------------------
+struct Allocator {
+    sait_allocator user{};
+    bool has_user = false;
+    void *alloc(size_t bytes);
+    void release(void *p);
+};
+
+class DevBuf {
+  public:
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            reset();
+            p_ = o.p_;
+            bytes_ = o.bytes_;
+            a_ = o.a_;
+            o.p_ = nullptr;
+            o.bytes_ = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void alloc(Allocator *a, size_t bytes);
+    void reset();
+    template <class T> T *as() const { return static_cast<T *>(p_); }
+    size_t bytes() const { return bytes_; }
+    bool empty() const { return p_ == nullptr; }
+
+  private:
+    void *p_ = nullptr;
+    size_t bytes_ = 0;
+    Allocator *a_ = nullptr;
+};
+
+// Host CSR (int32 pointers/indices, FP64 values).
+struct HostCsr {
+    int64_t n = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    int64_t nnz() const { return rp.empty() ? 0 : rp.back(); }
+};
+
+// Device CSR; `v` is FP64, `vs` the stored copy in the storage precision
+// (points at `v` for SAIT_F64).
+struct DevCsr {
+    int64_t n = 0, nnz = 0;
+    int precision = SAIT_F64;
+    DevBuf rp, ci, v, vs;
+    const void *stored() const { return precision == SAIT_F64 ? v.as<void>() : vs.as<void>(); }
+};
+
+// ---------------------------------------------------------------------------
+// Host-side routines (ilu_host.cpp)
+// ---------------------------------------------------------------------------
+void validate_csr(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const char *what);
+void host_ilu0(const HostCsr &A, HostCsr &L, HostCsr &U);
+void host_ilut(const HostCsr &A, double tau, int fill, HostCsr &L, HostCsr &U);
+
+// ---------------------------------------------------------------------------
+// SpGEMM construction of the SAIT factors (k_spgemm.hip)
+// ---------------------------------------------------------------------------
+struct SaitParams {
+    int m = 3;
+    double tau = 1e-2;
+    int cap = 0;        // 0: no per-row cap
+    int pattern_p = -1; // >= 0: SAIT_Pat(p, m)
+    int precision = SAIT_F64;
+};
+
+// Upload a host CSR.
+void upload_csr(Allocator *a, const HostCsr &h, DevCsr &d, hipStream_t s);
+// Download a device CSR (FP64 values).
+void download_csr(const DevCsr &d, HostCsr &h, hipStream_t s);
+// Build M ~ T^-1 for a device-resident triangular T.
+void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCsr &M, hipStream_t s);
+// One unscaled pass M_next = drop(T~ M_prev + I) (test entry point).
+void sait_single_pass(Allocator *a, const DevCsr &T, const DevCsr &Mprev, double tau, int cap,
+                      DevCsr &Mnext, hipStream_t s);
+// Device exclusive scan of int64 counts: out[0..n] (out[n] = total).
+void scan_exclusive_i64(Allocator *a, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// CSR transpose (structure and FP64 values); output rows sorted.
+void transpose_csr(Allocator *a, const DevCsr &M, DevCsr &Mt, hipStream_t s);
+// perm such that Mt.v[q] = M.v[perm[q]] for Mt = transpose_csr(M).
+void transpose_perm(Allocator *a, const DevCsr &M, DevBuf &perm, hipStream_t s);
+// dst[q] = src[perm[q]], q < nnz.
+void gather_values(int64_t nnz, const int *perm, const double *src, double *dst, hipStream_t s);
+// Re-derive the stored-precision copy `vs` of M from its FP64 values.
+void cast_values(Allocator *a, DevCsr &M, int precision, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// SpMV / SpMM (k_spmv.hip)
+// ---------------------------------------------------------------------------
+enum class XKind { F64, F32 };   // element type of the gathered input vector
+enum class YKind { F64, F32 };   // element type of the output vector
+
+// y = M x for one CSR factor; lanes = lanes per row (1..64, power of two).
+// `resid_b` != nullptr: y = b - M x (FP64 only).
+void spmv(const DevCsr &M, const void *x, XKind xk, void *y, YKind yk, int nrhs, int64_t ldx, int64_t ldy,
+          int lanes, hipStream_t s, const double *resid_b = nullptr);
+int default_lanes(const DevCsr &M);
+
+// ---------------------------------------------------------------------------
+// Krylov building blocks (k_krylov.hip)
+// ---------------------------------------------------------------------------
+struct GmresState;   // device-resident per-solve state (k_krylov.hip)
+struct Krylov;       // host-side driver workspace
+
+}  // namespace sait

@@ -1,0 +1,49 @@
+// Device-resident restarted (F)GMRES state and its host driver.
+#pragma once
+
+#include "sait_internal.h"
+
+namespace sait {
+
+// Lives in device memory; the array pointers point into one device buffer.
+struct GmresDev {
+    double *H;    // (restart+1) x restart Hessenberg / R factor, column-major
+    double *cs, *sn, *g, *y, *h1, *h2;
+    double nb, beta, est, inv_hn, wpre2, rtol;
+    int restart, maxit, iters, jc, done, reorth;
+};
+
+// Operators of one solve: A (FP64) and the preconditioner z = M2 (M1 v).
+struct Ops {
+    const DevCsr *A = nullptr, *M1 = nullptr, *M2 = nullptr;
+    int lanesA = 8, lanes1 = 8, lanes2 = 8;
+    int precision = SAIT_F64;
+};
+
+class Solver {
+  public:
+    Solver() = default;
+    Solver(const Solver &) = delete;
+    Solver &operator=(const Solver &) = delete;
+    ~Solver();
+    int solve(Allocator *a, const Ops &ops, const double *b, double *x, const sait_solve_opts &o,
+              sait_solve_info *info, hipStream_t s);
+
+  private:
+    void ensure(Allocator *a, int64_t n, int restart, bool flexible, int precision);
+    void apply_prec(const Ops &ops, const double *in, double *out, hipStream_t s);
+    static void fill_info(sait_solve_info *info, int iters, int restarts, int status, double est, double relres);
+
+    int64_t n_ = -1, ldv_ = 0;
+    int restart_ = 0;
+    DevBuf V_, Z_, zt_, ut_, y32_, arr_, st_, part_, counters_;
+    void *mailbox_ = nullptr;
+};
+
+// dst[r*ldd] = src[r*lds] for r < n.
+void copy_strided(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, hipStream_t s);
+
+// grad[p] = -lambda[row p] * x[col p] over the stored entries of A.
+void grad_values(const DevCsr &A, const double *lambda, const double *x, double *grad, hipStream_t s);
+
+}  // namespace sait

@@ -1,0 +1,144 @@
+"""GPU parity of the SAIT construction against the CPU oracle.
+
+The device builds M_L, M_U with the same summation order as the oracle
+(products in increasing l, explicitly rounded), so patterns must be
+identical and values agree to 1e-12 relative (bitwise in practice); the
+binary32 / bfloat16 stored values must equal the oracle's roundings bit
+for bit.  Host ILU factors of the library must equal the oracle's.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from paper_2106_12836_amd import SaitError, SaitPreconditioner, sait_debug_step
+from workloads import (Csr, config, convdiff2d_upwind, poisson2d, poisson3d, random_diag_dominant,
+                       random_triangular)
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def _cmp_csr(rp, ci, v, ref: Csr, what):
+    np.testing.assert_array_equal(rp, ref.rp, err_msg=f"{what}: row pointers")
+    np.testing.assert_array_equal(ci, ref.ci, err_msg=f"{what}: columns")
+    scale = np.maximum(np.abs(ref.v), 1e-300)
+    err = np.abs(v - ref.v) / scale
+    assert err.max(initial=0.0) <= RTOL, f"{what}: max rel err {err.max()}"
+
+
+def _oracle_factors(A, ilu, m, tau, cap=0, p=-1, ilut=(1e-3, 10)):
+    L, U = oracle.ilu0(A) if ilu == "ilu0" else oracle.ilut(A, *ilut)
+    if p >= 0:
+        return L, U, oracle.sait_pat(L, p, m), oracle.sait_pat(U, p, m)
+    return L, U, oracle.sait_thr(L, tau, m, cap), oracle.sait_thr(U, tau, m, cap)
+
+
+CASES = [
+    ("c1-small", lambda: config("c1", small=True)["A"], dict(m=3, tau=1e-2)),
+    ("c1", lambda: config("c1")["A"], dict(m=3, tau=1e-2)),
+    ("c3-small", lambda: config("c3", small=True)["A"], dict(m=3, tau=1e-3)),
+    ("poisson3d-9-tau0-m6", lambda: poisson3d(9), dict(m=6, tau=0.0)),
+    ("rdd-ragged", lambda: random_diag_dominant(3001, 8, band=300, seed=3), dict(m=3, tau=1e-2)),
+    ("rdd-wide", lambda: random_diag_dominant(2000, 8, band=None, seed=4), dict(m=2, tau=0.0)),
+    ("convdiff-ilut", lambda: convdiff2d_upwind(40, 10.0), dict(m=4, tau=1e-3, ilu_kind="ilut")),
+    ("cap5", lambda: poisson3d(7), dict(m=4, tau=0.0, max_nnz_row=5)),
+    ("pat2", lambda: poisson3d(8), dict(m=3, tau=0.0, pattern_p=2)),
+    ("m0", lambda: poisson2d(9), dict(m=0, tau=0.1)),
+    ("n1", lambda: Csr(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])), dict(m=2, tau=0.1)),
+]
+
+
+@pytest.mark.parametrize("name,maker,opts", CASES, ids=[c[0] for c in CASES])
+def test_factors_match_oracle(name, maker, opts):
+    print(f"[test_factors_match_oracle] {name}", flush=True)
+    A = maker()
+    ilu = opts.get("ilu_kind", "ilu0")
+    L, U, ML, MU = _oracle_factors(A, ilu, opts["m"], opts["tau"], opts.get("max_nnz_row", 0),
+                                   opts.get("pattern_p", -1))
+    pre = SaitPreconditioner(A, **opts)
+    try:
+        for which, ref in (("L", L), ("U", U)):
+            rp, ci, v = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v, ref.v)  # same operations in the same order
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, _ = pre.export(which)
+            _cmp_csr(rp, ci, v, ref, which)
+        q = pre.query()
+        assert q["nnz_ML"] == ML.nnz and q["nnz_MU"] == MU.nnz
+        assert abs(q["ratio_L"] - ML.nnz / L.nnz) < 1e-15
+    finally:
+        pre.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_stored_values_bit_exact(prec):
+    print(f"[test_stored_values_bit_exact] {prec}", flush=True)
+    A = config("c3", small=True)["A"]
+    L, U, ML, MU = _oracle_factors(A, "ilu0", 3, 1e-3)
+    pre = SaitPreconditioner(A, m=3, tau=1e-3, precision=prec)
+    try:
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, stored = pre.export(which)
+            want = oracle.round_f32(ref.v) if prec == "f32" else oracle.round_bf16(ref.v)
+            np.testing.assert_array_equal(stored.view(want.dtype), want)
+    finally:
+        pre.close()
+
+
+def test_dense_rows_all_tiers():
+    # tau = 0 with m = n-1 on a dense-ish triangular matrix: rows reach
+    # thousands of candidate products (LDS tiers and the global fallback),
+    # and the result must be the exact inverse (Eq. T_inverse).
+    print("[test_dense_rows_all_tiers]", flush=True)
+    for lower in (True, False):
+        T = random_triangular(160, 0.5, 11, lower=lower, diag_range=(2.0, 3.0))
+        # one pass at a time through the debug entry point (T itself as input)
+        Mk = oracle.identity(160)
+        for k in range(12):
+            rp, ci, v = sait_debug_step(160, (T.rp, T.ci, T.v), (Mk.rp, Mk.ci, Mk.v), 0.0)
+            ref = oracle.sait_step(T, Mk, 0.0)
+            _cmp_csr(rp, ci, v, ref, f"pass {k}")
+            Mk = ref
+        # after 159 passes the scaled series is the exact inverse
+        Tinv = np.linalg.inv(T.to_scipy().toarray())
+        assert np.abs(oracle.sait_thr(T, 0.0, 159).to_scipy().toarray() - Tinv).max() < 1e-10 * np.abs(Tinv).max()
+
+
+@pytest.mark.parametrize("tau,cap", [(0.0, 0), (1e-2, 0), (0.05, 0), (0.0, 4), (1e-3, 7)])
+def test_stepwise_harness(tau, cap):
+    # Each device pass is fed the oracle's previous M (never the reverse).
+    print(f"[test_stepwise_harness] tau={tau} cap={cap}", flush=True)
+    A = random_diag_dominant(1500, 8, band=100, seed=21)
+    L, U = oracle.ilu0(A)
+    for T in (L, U):
+        M = oracle.identity(A.n)
+        for k in range(4):
+            rp, ci, v = sait_debug_step(A.n, (T.rp, T.ci, T.v), (M.rp, M.ci, M.v), tau, cap)
+            ref = oracle.sait_step(T, M, tau, cap)
+            _cmp_csr(rp, ci, v, ref, f"pass {k}")
+            M = ref
+
+
+def test_build_errors():
+    print("[test_build_errors]", flush=True)
+    A = Csr(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([0.0, 1.0, 1.0, 2.0]))
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(A)
+    assert e.value.status == -2  # zero pivot
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(poisson2d(4), tau=1.0)
+    assert e.value.status == -1
+    bad = Csr(2, np.array([0, 2, 3], np.int32), np.array([1, 0, 1], np.int32), np.array([1.0, 1.0, 1.0]))
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(bad)
+    assert e.value.status == -1  # unsorted columns
+    nanA = poisson2d(3)
+    nanA.v[0] = np.nan
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(nanA)
+    assert e.value.status == -3
