@@ -199,11 +199,23 @@ void sait_destroy(sait_handle h);
 const char *sait_last_error(void);
 
 /*
- * Apply-kernel shape: lanes per CSR row (1, 2, 4, ..., 64) used for M_L
- * and M_U.  sait_autotune times the candidates on the handle's factors
- * (device work on hip_stream, synchronises it) and keeps the fastest;
- * sait_set_apply_lanes overrides (0 = keep).  sait_get_apply_lanes reports.
+ * Apply-kernel shape for M_L and M_U:
+ *   SAIT_SHAPE_SELL (-64) / -65: sliced ELL (64-row slices, one row per
+ *     lane), 2 / 1 groups of 4 entries per pipeline stage -- the default
+ *     when slicing pads at most 1/8 of the entries;
+ *   SAIT_SHAPE_STREAM (-16) / -8: LDS-staged CSR with 4088 / 2040-entry
+ *     chunks;
+ *   a power of two 1..64: wavefront CSR with that many lanes per row.
+ * The sliced-ELL and LDS-staged kernels compute each row as the left-to-
+ * right sum of separately rounded products in column order.  Blocks of
+ * right-hand sides always use the wavefront kernel (8 lanes per row for a
+ * negative shape).  sait_autotune times every candidate on the handle's
+ * factors and A (device work on hip_stream, synchronises it) and keeps the
+ * fastest; sait_set_apply_lanes overrides (0 = keep); sait_get_apply_lanes
+ * reports.
  */
+#define SAIT_SHAPE_SELL (-64)
+#define SAIT_SHAPE_STREAM (-16)
 int sait_autotune(sait_handle h, int nrhs, void *hip_stream);
 int sait_set_apply_lanes(sait_handle h, int lanes_L, int lanes_U);
 int sait_get_apply_lanes(sait_handle h, int *lanes_L, int *lanes_U);
@@ -216,6 +228,14 @@ int sait_get_apply_lanes(sait_handle h, int *lanes_L, int *lanes_U);
  */
 int sait_time_apply(sait_handle h, const double *r, double *z, int reps, void *hip_stream,
                     double *ms_L, double *ms_U, double *ms_apply);
+
+/*
+ * Measurement aid: copy `bytes` (a multiple of 16) from src to dst (device,
+ * 16-byte aligned, not overlapping) with a plain streaming kernel, on
+ * hip_stream.  Its rate is the practically achievable HBM bandwidth the
+ * SpMV rates are compared with.
+ */
+int sait_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
 
 /*
  * Test entry point: one unscaled Horner pass on the device,

@@ -18,6 +18,7 @@ from .sait import (  # noqa: F401
     sait_apply,
     sait_autotune,
     sait_build,
+    sait_copy,
     sait_debug_step,
     sait_destroy,
     sait_export,

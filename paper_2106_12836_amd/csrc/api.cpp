@@ -46,8 +46,10 @@ void Allocator::release(void *p) {
 void DevBuf::alloc(Allocator *a, size_t bytes) {
     reset();
     a_ = a;
+    // 64 bytes of tail padding: vector loads of the last aligned group of
+    // entries may extend past the logical end of an array
     bytes_ = std::max<size_t>(bytes, 64);
-    p_ = a->alloc(bytes_);
+    p_ = a->alloc(bytes_ + 64);
 }
 
 void DevBuf::reset() {
@@ -239,9 +241,17 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
             cast_values(&h->alloc, h->MLt, opts.precision, s);
             cast_values(&h->alloc, h->MUt, opts.precision, s);
             h->has_transpose = true;
+            for (DevCsr *M : {&h->At, &h->MLt, &h->MUt}) {
+                prepare_stream(&h->alloc, *M, s);
+                prepare_sell(&h->alloc, *M, s);
+            }
             h->lanesAt = default_lanes(h->At);
             h->lanesLt = default_lanes(h->MLt);
             h->lanesUt = default_lanes(h->MUt);
+        }
+        for (DevCsr *M : {&h->A, &h->ML, &h->MU}) {
+            prepare_stream(&h->alloc, *M, s);
+            prepare_sell(&h->alloc, *M, s);
         }
         h->lanesA = default_lanes(h->A);
         h->lanesL = default_lanes(h->ML);
@@ -385,8 +395,10 @@ void sait_destroy(sait_handle h) {
 int sait_set_apply_lanes(sait_handle h, int lanes_L, int lanes_U) {
     return guard([&]() -> int {
         if (!h) fail(SAIT_E_INVALID, "null handle");
-        auto ok = [](int l) { return l == 0 || (l >= 1 && l <= 64 && (l & (l - 1)) == 0); };
-        if (!ok(lanes_L) || !ok(lanes_U)) fail(SAIT_E_INVALID, "lanes must be 0 or a power of two in 1..64");
+        auto ok = [](int l) { return l == 0 || valid_shape(l); };
+        if (!ok(lanes_L) || !ok(lanes_U))
+            fail(SAIT_E_INVALID, "apply shape must be 0 (keep), -64/-65 (sliced ELL), -8/-16 (LDS-staged CSR) or a "
+                                 "power of two in 1..64");
         if (lanes_L) h->lanesL = lanes_L;
         if (lanes_U) h->lanesU = lanes_U;
         return SAIT_OK;
@@ -420,7 +432,9 @@ int sait_autotune(sait_handle h, int nrhs, void *hip_stream) {
         auto best_for = [&](const DevCsr &M, XKind xk, YKind yk) {
             int best = default_lanes(M);
             float best_ms = 1e30f;
-            for (int l = 1; l <= 64; l <<= 1) {
+            const int shapes[] = {kSell, kSell1, kStream8, kStream, 1, 2, 4, 8, 16, 32, 64};
+            for (int l : shapes) {
+                if (l < 0 && nrhs != 1) continue;
                 spmv(M, x.as<void>(), xk, y.as<void>(), yk, nrhs, nrhs, nrhs, l, s);  // warm-up
                 SAIT_HIP(hipEventRecord(e0, s));
                 for (int r = 0; r < 5; ++r) spmv(M, x.as<void>(), xk, y.as<void>(), yk, nrhs, nrhs, nrhs, l, s);
@@ -482,6 +496,17 @@ int sait_time_apply(sait_handle h, const double *r, double *z, int reps, void *h
         if (ms_L) *ms_L = sl / reps;
         if (ms_U) *ms_U = su / reps;
         if (ms_apply) *ms_apply = sa / reps;
+        return SAIT_OK;
+    });
+}
+
+int sait_copy(const void *src, void *dst, size_t bytes, void *hip_stream) {
+    return guard([&]() -> int {
+        if (bytes % 16) fail(SAIT_E_INVALID, "bytes must be a multiple of 16");
+        if (bytes && (!src || !dst)) fail(SAIT_E_INVALID, "null pointer");
+        if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+            fail(SAIT_E_INVALID, "pointers must be 16-byte aligned");
+        copy_bytes(src, dst, bytes, as_stream(hip_stream));
         return SAIT_OK;
     });
 }

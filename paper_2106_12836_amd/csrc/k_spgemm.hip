@@ -32,8 +32,15 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 
-__device__ __forceinline__ double dmul(double a, double b) { return __dmul_rn(a, b); }
-__device__ __forceinline__ double dadd(double a, double b) { return __dadd_rn(a, b); }
+// Separately rounded product and sum (never contracted into an FMA).
+__device__ __forceinline__ double dmul(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double dadd(double a, double b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
 
 // ---------------------------------------------------------------------------
 // Jacobi split: dinv and T~ (row i of T~ = row i of T without its diagonal).
@@ -89,14 +96,24 @@ __global__ void k_count(int n, const int *__restrict__ trp, const int *__restric
 
 // Tier of a row by candidate count.
 constexpr int kTierCap0 = 64, kTierCap1 = 256, kTierCap2 = 2048;
+// Slots are claimed per block (LDS counters, then one global atomic per tier
+// and block), so the global counters see gridDim.x updates, not n.
 __global__ void k_classify(int n, const int64_t *__restrict__ cnt, int *__restrict__ tier_n,
                            int *__restrict__ lists) {
+    __shared__ int lcount[4], lbase[4];
+    if (threadIdx.x < 4) lcount[threadIdx.x] = 0;
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t c = cnt[i];
-    const int t = c <= kTierCap0 ? 0 : c <= kTierCap1 ? 1 : c <= kTierCap2 ? 2 : 3;
-    const int slot = atomicAdd(&tier_n[t], 1);
-    lists[(int64_t)t * n + slot] = i;
+    int t = 0, slot = 0;
+    if (i < n) {
+        const int64_t c = cnt[i];
+        t = c <= kTierCap0 ? 0 : c <= kTierCap1 ? 1 : c <= kTierCap2 ? 2 : 3;
+        slot = atomicAdd(&lcount[t], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && lcount[threadIdx.x]) lbase[threadIdx.x] = atomicAdd(&tier_n[threadIdx.x], lcount[threadIdx.x]);
+    __syncthreads();
+    if (i < n) lists[(int64_t)t * n + lbase[t] + slot] = i;
 }
 
 // ---------------------------------------------------------------------------
@@ -715,7 +732,7 @@ void make_identity(Allocator *a, int n, DevCsr &M, hipStream_t s) {
 // Scale columns by dinv (used when m == 0 or when the last pass is not fused).
 __global__ void k_scale_cols(int64_t nnz, const int *__restrict__ ci, double *__restrict__ v, const double *__restrict__ dinv) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nnz) v[p] = __dmul_rn(v[p], dinv[ci[p]]);
+    if (p < nnz) v[p] = dmul(v[p], dinv[ci[p]]);
 }
 
 }  // namespace

@@ -88,6 +88,19 @@ struct DevCsr {
     int64_t n = 0, nnz = 0;
     int precision = SAIT_F64;
     DevBuf rp, ci, v, vs;
+    // Row blocks of the LDS-staged SpMV, one partition per chunk size (2040
+    // and 4088 entries): block b covers rows [brow[b], brow[b+1]) -- at most
+    // 256 rows and one chunk of entries, or one longer row alone.
+    DevBuf brow[2];
+    int64_t nblk[2] = {0, 0};
+    // Sliced-ELL copy for the one-row-per-lane kernel: slice s holds rows
+    // 64 s .. 64 s + 63 (one wavefront), padded to the slice's longest row
+    // rounded up to a multiple of 4; entry k of row 64 s + l is stored at
+    // sell_ptr[s] + (k / 4) * 256 + 4 l + k % 4.  Padding holds column 0 and
+    // value 0 and is never used (row lengths come from rp).  Values are in
+    // the storage precision.
+    DevBuf sell_ptr, sell_ci, sell_v;
+    int64_t nslices = 0, sell_nnz = 0;
     const void *stored() const { return precision == SAIT_F64 ? v.as<void>() : vs.as<void>(); }
 };
 
@@ -140,6 +153,16 @@ enum class YKind { F64, F32 };   // element type of the output vector
 void spmv(const DevCsr &M, const void *x, XKind xk, void *y, YKind yk, int nrhs, int64_t ldx, int64_t ldy,
           int lanes, hipStream_t s, const double *resid_b = nullptr);
 int default_lanes(const DevCsr &M);
+// Apply kernel shapes: > 0 lanes per row of the wavefront CSR kernel; < 0
+// the sliced-ELL (needs prepare_sell) or LDS-staged (needs prepare_stream)
+// kernels.
+constexpr int kStream8 = -8, kStream = -16;  // LDS-staged CSR, 2040 / 4088-entry chunks
+constexpr int kSell = -64, kSell1 = -65;     // sliced ELL, 2 / 1 groups of 4 entries per stage
+bool valid_shape(int shape);
+// Sliced-ELL copy of M's stored values (needs the storage cast done).
+void prepare_sell(Allocator *a, DevCsr &M, hipStream_t s);
+// Row blocks for the LDS-staged kernel (host pass over the row pointers).
+void prepare_stream(Allocator *a, DevCsr &M, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Krylov building blocks (k_krylov.hip)

@@ -43,6 +43,9 @@ class Solver {
 // dst[r*ldd] = src[r*lds] for r < n.
 void copy_strided(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, hipStream_t s);
 
+// Streaming device copy (bandwidth reference), bytes a multiple of 16.
+void copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t s);
+
 // grad[p] = -lambda[row p] * x[col p] over the stored entries of A.
 void grad_values(const DevCsr &A, const double *lambda, const double *x, double *grad, hipStream_t s);
 

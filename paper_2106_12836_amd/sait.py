@@ -29,7 +29,7 @@ PRECISIONS = {"f64": SAIT_F64, "f32": SAIT_F32, "bf16": SAIT_BF16}
 EXPORTED = (
     "sait_default_build_opts", "sait_default_solve_opts", "sait_build", "sait_apply", "sait_matvec",
     "sait_solve", "sait_set_values", "sait_grad_values", "sait_query", "sait_export", "sait_destroy", "sait_last_error",
-    "sait_autotune", "sait_set_apply_lanes", "sait_get_apply_lanes", "sait_time_apply", "sait_debug_step",
+    "sait_autotune", "sait_set_apply_lanes", "sait_get_apply_lanes", "sait_time_apply", "sait_debug_step", "sait_copy",
 )
 
 
@@ -94,6 +94,7 @@ def lib():
         L.sait_set_apply_lanes.argtypes = [vp, C.c_int, C.c_int]
         L.sait_get_apply_lanes.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sait_time_apply.argtypes = [vp, vp, vp, C.c_int, vp, f64p, f64p, f64p]
+        L.sait_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.sait_debug_step.argtypes = [i64, i32p, i32p, f64p, i32p, i32p, f64p, C.c_double, C.c_int, i64,
                                       i32p, i32p, f64p, C.POINTER(C.c_int64)]
         _LIB = L
@@ -252,6 +253,14 @@ def sait_time_apply(h, r, z, reps=10, stream=None):
     _check(lib().sait_time_apply(h, _dptr(r), _dptr(z), int(reps), _stream(stream), C.byref(a), C.byref(b),
                                  C.byref(c)))
     return a.value, b.value, c.value
+
+
+def sait_copy(src, dst, stream=None):
+    """dst <- src with the library's streaming copy kernel (torch tensors)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    return _check(lib().sait_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, _stream(stream)))
 
 
 def sait_debug_step(n, T, M, tau, max_nnz_row=0):

@@ -109,6 +109,39 @@ def test_dense_rows_all_tiers():
         assert np.abs(oracle.sait_thr(T, 0.0, 159).to_scipy().toarray() - Tinv).max() < 1e-10 * np.abs(Tinv).max()
 
 
+def test_long_rows_apply():
+    # rows longer than one LDS chunk (4088 entries) are processed chunk by
+    # chunk; results stay bit-exact with the oracle for every exact shape
+    print("[test_long_rows_apply]", flush=True)
+    import torch
+    from paper_2106_12836_amd import sait_set_apply_lanes
+    n = 9000
+    rng = np.random.default_rng(5)
+    rows = [np.arange(n)]
+    cols = [np.arange(n)]
+    dense_rows = [4000, 8999]
+    for r in dense_rows:
+        c = np.arange(r)
+        rows.append(np.full(r, r))
+        cols.append(c)
+    rr = np.concatenate(rows)
+    cc = np.concatenate(cols)
+    vals = np.where(rr == cc, 4.0, rng.uniform(-1, 1, rr.size) * 1e-3)
+    A = Csr.from_scipy(sp.csr_matrix((vals, (rr, cc)), shape=(n, n)))
+    L, U, ML, MU = _oracle_factors(A, "ilu0", 1, 0.0)
+    assert max(np.diff(ML.rp)) > 4088
+    pre = SaitPreconditioner(A, m=1, tau=0.0)
+    try:
+        r = np.random.default_rng(2).uniform(-1, 1, n)
+        zr = oracle.apply(ML, MU, r)
+        for shape in (-64, -65, -8, -16):
+            sait_set_apply_lanes(pre.handle, shape, shape)
+            z = pre.apply(torch.tensor(r, device="cuda:0")).cpu().numpy()
+            np.testing.assert_array_equal(z, zr)
+    finally:
+        pre.close()
+
+
 @pytest.mark.parametrize("tau,cap", [(0.0, 0), (1e-2, 0), (0.05, 0), (0.0, 4), (1e-3, 7)])
 def test_stepwise_harness(tau, cap):
     # Each device pass is fed the oracle's previous M (never the reverse).

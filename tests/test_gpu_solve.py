@@ -45,8 +45,13 @@ APPLY_CASES = [
 ]
 
 
+# apply shapes: -64/-65 sliced ELL, -8/-16 LDS-staged CSR (all four exact
+# column-order sums), > 0 lanes per row of the wavefront CSR kernel
+SHAPES = [-64, -65, -8, -16, 1, 4, 8, 16, 64]
+
+
 @pytest.mark.parametrize("name,maker,tau,m", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
-@pytest.mark.parametrize("lanes", [1, 4, 8, 16, 64])
+@pytest.mark.parametrize("lanes", SHAPES)
 def test_apply_f64(name, maker, tau, m, lanes):
     print(f"[test_apply_f64] {name} lanes={lanes}", flush=True)
     A = maker()
@@ -58,6 +63,9 @@ def test_apply_f64(name, maker, tau, m, lanes):
         r = uniform_vector(A.n, 7)
         z = pre.apply(_t(r)).cpu().numpy()
         zr = oracle.apply(ML, MU, r)
+        if lanes < 0:
+            # rounded products summed in column order: the oracle's arithmetic
+            np.testing.assert_array_equal(z, zr)
         K = max(np.diff(ML.rp).max(), np.diff(MU.rp).max()) + 1
         bound = 4 * K * 2.0 ** -53 * (abs(_sp(MU)) @ (abs(_sp(ML)) @ np.abs(r)))
         assert np.all(np.abs(z - zr) <= bound + 1e-300)
@@ -92,13 +100,15 @@ def test_apply_block(nrhs):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("nrhs", [1, 4])
-def test_apply_mixed_bound(prec, nrhs):
-    print(f"[test_apply_mixed_bound] {prec} nrhs={nrhs}", flush=True)
+@pytest.mark.parametrize("nrhs,shape", [(1, -64), (1, -65), (1, -8), (1, -16), (4, -16)])
+def test_apply_mixed_bound(prec, nrhs, shape):
+    print(f"[test_apply_mixed_bound] {prec} nrhs={nrhs} shape={shape}", flush=True)
     A = config("c3", small=True)["A"]
     L, U, ML, MU = _factors(A, 1e-3, 3)
     pre = SaitPreconditioner(A, m=3, tau=1e-3, precision=prec)
     try:
+        from paper_2106_12836_amd import sait_set_apply_lanes
+        sait_set_apply_lanes(pre.handle, shape, shape)
         R = uniform_vector(A.n, 9, k=nrhs)
         Z = pre.apply(_t(R if nrhs > 1 else R[:, 0])).cpu().numpy().reshape(A.n, nrhs)
         f1 = oracle.storage_values(ML, prec).astype(np.float64)
@@ -112,6 +122,9 @@ def test_apply_mixed_bound(prec, nrhs):
             bound = 2 * gam * (abs(_sp(MU, f2)) @ (abs(_sp(ML, f1)) @ np.abs(r32))) * (1 + 4 * u)
             assert np.all(np.abs(Z[:, k] - zstar) <= bound)
             zo = oracle.apply_f32acc(ML, f1.astype(np.float32), MU, f2.astype(np.float32), R[:, k])
+            if nrhs == 1:
+                # LDS-staged kernel: binary32 products and sums in the oracle's order
+                np.testing.assert_array_equal(Z[:, k], zo)
             assert np.linalg.norm(Z[:, k] - zo) <= 1e-5 * np.linalg.norm(zo)
     finally:
         pre.close()
