@@ -59,6 +59,29 @@ def kernel_name(shape):
     return f"k_spmv<{shape}, double> (wavefront CSR)"
 
 
+def measured_traffic(shape):
+    """Per-launch HBM bytes of the FP64 apply SpMV from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the streaming-copy
+    calibration recorded there), or None when the summary does not cover
+    this kernel or the kernel source changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_spmv_sell_c3_128_traffic.txt")
+    src = os.path.join(ROOT, "paper_2106_12836_amd", "csrc", "k_spmv.hip")
+    if shape != -64 or not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = {}
+    for line in open(path):
+        if line.startswith("f64:"):
+            fields.update(kv.split("=") for kv in line[4:].split())
+        elif line.startswith("k_spmv_sha256="):
+            fields["sha"] = line.strip().split("=")[1]
+    if fields.get("sha") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def copy_bandwidth(torch, dev, mib=1024, reps=20):
     """Rate of the library's plain streaming copy (read + write bytes)."""
     from paper_2106_12836_amd import sait_copy
@@ -113,6 +136,7 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -121,7 +145,7 @@ def main():
 
     import torch
 
-    from paper_2106_12836_amd import SaitPreconditioner, sait_time_apply
+    from paper_2106_12836_amd import SaitPreconditioner, sait_get_apply_lanes, sait_time_apply
     from workloads import config, poisson3d, spmv_rhs, uniform_vector
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -140,7 +164,7 @@ def main():
         pre = SaitPreconditioner(A, m=m, tau=tau, precision=prec)
         torch.cuda.synchronize()
         t_build = time.time() - t0
-        lanes = pre.autotune()
+        lanes = pre.autotune() if not args.no_autotune else sait_get_apply_lanes(pre.handle)
         q = pre.query()
         pres[prec] = pre
         results[prec] = dict(build_s=round(t_build, 3), lanes=lanes, nnz_ML=q["nnz_ML"], nnz_MU=q["nnz_MU"],
@@ -185,7 +209,8 @@ def main():
             avg_launch_ms = (ms_L + ms_U) / 2
             achieved = per_launch_bytes / (avg_launch_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(results["f64"]["lanes"][0]),
                     "kernel": kernel_name(results["f64"]["lanes"][0]) + " (SpMV of M_L and M_U)",
                     "bytes_per_launch": per_launch_bytes, "avg_launch_ms": round(avg_launch_ms, 5)}
     print(f"[bench] per-precision apply: {json.dumps(apply_stats)}", file=sys.stderr, flush=True)
