@@ -76,6 +76,7 @@ struct sait_handle_s {
     DevBuf tmp;     // apply intermediate
     DevBuf At_perm; // At.v[q] = A.v[At_perm[q]]
     Solver solver;
+    BatchedSolver batched;
 };
 
 namespace {
@@ -298,8 +299,28 @@ int sait_solve(sait_handle h, const double *b, double *x, int nrhs, int64_t ld, 
         sait_solve_opts opts;
         sait_default_solve_opts(&opts);
         if (o) opts = *o;
-        if (h->nsys != 1 || nrhs != 1 || ld != 1)
-            fail(SAIT_E_INVALID, "batched solves (nsys > 1 or nrhs > 1) are not available in this build");
+        if (h->nsys != 1 || nrhs != 1 || ld != 1) {
+            if (transpose) fail(SAIT_E_INVALID, "batched solves are not transposed");
+            BatchedOps bo;
+            bo.A = &h->A;
+            bo.ML = &h->ML;
+            bo.MU = &h->MU;
+            bo.sys_ptr = h->sys_ptr;
+            // groups of at most 8 right-hand sides per persistent launch
+            std::vector<sait_solve_info> tmp;
+            int status = SAIT_OK;
+            for (int k0 = 0; k0 < nrhs; k0 += 8) {
+                const int R = std::min(8, nrhs - k0);
+                tmp.assign((size_t)h->nsys * R, sait_solve_info{});
+                const int st = h->batched.solve(&h->alloc, bo, b + k0, x + k0, R, ld, opts, tmp.data(),
+                                                as_stream(hip_stream));
+                if (st != SAIT_OK) status = st;
+                if (info)
+                    for (int sy = 0; sy < h->nsys; ++sy)
+                        for (int q = 0; q < R; ++q) info[(size_t)sy * nrhs + k0 + q] = tmp[(size_t)sy * R + q];
+            }
+            return status;
+        }
         Ops ops;
         ops.A = transpose ? &h->At : &h->A;
         ops.M1 = transpose ? &h->MUt : &h->ML;

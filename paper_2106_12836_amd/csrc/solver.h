@@ -40,6 +40,30 @@ class Solver {
     void *mailbox_ = nullptr;
 };
 
+// Operators of a batched solve: block-diagonal A and its SAIT factors (FP64,
+// sliced-ELL copies prepared) and the first row of every system.
+struct BatchedOps {
+    const DevCsr *A = nullptr, *ML = nullptr, *MU = nullptr;
+    std::vector<int64_t> sys_ptr;
+};
+
+// One persistent cooperative launch solving every (system, right-hand side)
+// pair with its own restarted right-preconditioned GMRES (k_batched.hip).
+class BatchedSolver {
+  public:
+    BatchedSolver();
+    BatchedSolver(const BatchedSolver &) = delete;
+    BatchedSolver &operator=(const BatchedSolver &) = delete;
+    ~BatchedSolver();
+    // R <= 8 right-hand sides, b and x row-major n x ld (device)
+    int solve(Allocator *a, const BatchedOps &ops, const double *b, double *x, int R, int64_t ld,
+              const sait_solve_opts &o, sait_solve_info *info, hipStream_t s);
+
+  private:
+    struct Impl;
+    Impl *impl_;
+};
+
 // dst[r*ldd] = src[r*lds] for r < n.
 void copy_strided(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t n, hipStream_t s);
 
