@@ -8,7 +8,10 @@ apply divided by the measured time per step (GB/s), beside the fraction of
 the 8 TB/s HBM peak.  The second half of the metric -- time to a 1e-10
 true relative residual with FGMRES(40), FP32 / BF16 factors against the
 FP64 form -- is measured after the timed loop and reported in
-`time_to_residual`.
+`time_to_residual`.  `batched` reports the batched workload (256 anisotropic
+2D systems x 8 right-hand sides, GMRES(30) to 1e-8, one persistent launch):
+wall time, systems/s, pair-iterations/s and the modelled bytes per second
+(batched_bytes).
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -128,6 +131,82 @@ def cpu_baseline(A, tau, m, target_seconds=12.0):
     }
 
 
+def batched_bytes(sys_ptr, rp_A, rp_ML, rp_MU, iters, k, RP):
+    """Modelled HBM bytes of a batched solve (one persistent launch).
+
+    The launch runs in global cycles of up to k Arnoldi steps; system s takes
+    part in step j of cycle c while one of its pairs still has iterations
+    left there: steps_s(c) = max_q min(k, max(0, I_sq - k c)).  Per system
+    step (vec = rows_s * RP * 8 bytes, entries 12 bytes each):
+        SpMM chain  (nnz_ML + nnz_MU + nnz_A) * 12 + 6 vec
+        inner products over V_0..V_{j-1}, u, z   (j + 2) vec
+        update (reads V_0..V_{j-1}, u, z, writes two vectors)  (j + 4) vec
+    per cycle: the true residual nnz_A * 12 + 4 vec, after a full cycle
+    the closing inner products (k + 1) vec, and the cycle end
+    (steps + 1) vec + (nnz_ML + nnz_MU) * 12 + 7 vec.
+    """
+    total = 0.0
+    for s in range(len(sys_ptr) - 1):
+        r0, r1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
+        rows = r1 - r0
+        vec = rows * RP * 8.0
+        nA, nL, nU = (float(rp[r1] - rp[r0]) for rp in (rp_A, rp_ML, rp_MU))
+        I = np.asarray(iters[s])
+        ncyc = int(np.max((I + k - 1) // k)) if I.size else 0
+        for c in range(ncyc + 1):
+            total += nA * 12 + 4 * vec
+            if c == ncyc:
+                break
+            steps = int(np.max(np.minimum(k, np.maximum(0, I - k * c))))
+            j = np.arange(steps)
+            total += steps * ((nL + nU + nA) * 12 + 6 * vec) + float(np.sum(2 * j + 6)) * vec
+            if steps == k:
+                total += (k + 1) * vec
+            total += (steps + 1) * vec + (nL + nU) * 12 + 7 * vec
+    return total
+
+
+def batched_solve(torch, dev):
+    """Full batched workload: 256 anisotropic 2D systems (sides U{32..512}),
+    8 right-hand sides each, ILU(0) + SAIT_Thr(1e-2, 3), GMRES(30) to 1e-8,
+    all pairs in one persistent launch."""
+    from paper_2106_12836_amd import SaitPreconditioner
+    from workloads import config
+
+    t0 = time.time()
+    c = config("c4")
+    A, sp, Bh = c["A"], c["sys_ptr"], c["B"]
+    nsys, R = len(sp) - 1, Bh.shape[1]
+    t_gen = time.time() - t0
+    t0 = time.time()
+    pre = SaitPreconditioner(A, nsys=nsys, sys_ptr=sp, m=c["m"], tau=c["tau"])
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    Bt = torch.tensor(Bh, dtype=torch.float64, device=dev)
+    pre.solve(Bt, restart=c["restart"], maxit=2, rtol=c["rtol"])  # allocates the workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, infos = pre.solve(Bt, restart=c["restart"], rtol=c["rtol"])
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    its = np.array([i.iterations for i in infos]).reshape(nsys, R)
+    bytes_model = batched_bytes(sp, A.rp, pre.row_ptr("ML"), pre.row_ptr("MU"), its, c["restart"],
+                                1 if R == 1 else 2 if R == 2 else 4 if R <= 4 else 8)
+    out = dict(
+        workload=f"{nsys} anisotropic 2D systems (sides U{{32..512}}, n={A.n}), {R} RHS each, ILU(0) + "
+                 f"SAIT_Thr(1e-2, 3), GMRES({c['restart']}) to {c['rtol']}, one persistent launch",
+        seconds=round(ts, 4), build_s=round(t_build, 3), generate_s=round(t_gen, 2),
+        systems_per_s=round(nsys / ts, 3), pair_iterations=int(its.sum()),
+        pair_iterations_per_s=round(float(its.sum()) / ts, 1),
+        iterations_min_mean_max=[int(its.min()), round(float(its.mean()), 1), int(its.max())],
+        nonconverged=int(sum(i.status != 0 for i in infos)),
+        max_true_relres=max(i.true_relres for i in infos),
+        modelled_bytes=bytes_model, modelled_gbs=round(bytes_model / ts / 1e9, 1),
+        pct_hbm_peak=round(100 * bytes_model / ts / 1e9 / HBM_PEAK_GBS, 1))
+    pre.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +216,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 256-system solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -245,6 +325,12 @@ def main():
         roof["copy_kernel_gbs"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
 
+    batched = None
+    if not args.no_batched:
+        print("[bench] batched solve (256 systems x 8 RHS) ...", file=sys.stderr, flush=True)
+        batched = batched_solve(torch, dev)
+        print(f"[bench] batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
@@ -274,6 +360,7 @@ def main():
         "cpu_baseline": cpu,
         "apply_by_precision": apply_stats,
         "time_to_residual": ttr,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

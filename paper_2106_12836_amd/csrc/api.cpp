@@ -382,7 +382,14 @@ int sait_export(sait_handle h, int which, int32_t *row_ptr, int32_t *col_idx, do
         case SAIT_MAT_U: hc = &h->U_h; break;
         case SAIT_MAT_ML:
         case SAIT_MAT_MU:
-            download_csr(*dc, tmp, nullptr);
+            if (!col_idx && !val) {  // row pointers only: skip the entries
+                tmp.n = dc->n;
+                tmp.rp.resize(dc->n + 1);
+                SAIT_HIP(hipMemcpy(tmp.rp.data(), dc->rp.as<void>(), (dc->n + 1) * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost));
+            } else {
+                download_csr(*dc, tmp, nullptr);
+            }
             hc = &tmp;
             break;
         default: fail(SAIT_E_INVALID, "unknown matrix id");

@@ -225,6 +225,14 @@ def sait_export(h, which: int, stored: bool = False):
     return out
 
 
+def sait_export_row_ptr(h, which: int):
+    """Row pointers only (no entries are copied)."""
+    q = sait_query(h)
+    rp = np.empty(q["n"] + 1, dtype=np.int32)
+    _check(lib().sait_export(h, int(which), _ptr(rp, C.c_int32), None, None, None))
+    return rp
+
+
 def sait_destroy(h):
     if h:
         lib().sait_destroy(h)
@@ -382,6 +390,10 @@ class SaitPreconditioner:
                 s = sv[: 8 * nnz].view(np.float64).copy()
             return rp, ci, v, s
         return sait_export(self.handle, idx)
+
+    def row_ptr(self, which: str):
+        idx = {"A": SAIT_MAT_A, "L": SAIT_MAT_L, "U": SAIT_MAT_U, "ML": SAIT_MAT_ML, "MU": SAIT_MAT_MU}[which]
+        return sait_export_row_ptr(self.handle, idx)
 
     def autotune(self, nrhs: int = 1, stream=None):
         sait_autotune(self.handle, nrhs, stream)

@@ -109,3 +109,43 @@ def test_batched_maxit_and_restart_one():
             pre.solve(torch.tensor(B, device=DEV), restart=65)
     finally:
         pre.close()
+
+
+def test_batched_c4_full_size():
+    """The full batched workload (256 systems, sides U{32..512}, n = 24.25M,
+    8 RHS) in the launch the benchmark times: every pair converges, every
+    true relative residual (recomputed on the host in FP64) is below rtol,
+    and on sampled blocks -- the four smallest and one mid-sized system --
+    every pair takes the oracle's iteration count (+-1)."""
+    print("[test_batched_c4_full_size] generating", flush=True)
+    c = config("c4")
+    A, sys_ptr, B = c["A"], c["sys_ptr"], c["B"]
+    nsys, R = len(sys_ptr) - 1, B.shape[1]
+    pre = SaitPreconditioner(A, nsys=nsys, sys_ptr=sys_ptr, m=c["m"], tau=c["tau"])
+    try:
+        print("[test_batched_c4_full_size] solving", flush=True)
+        X, infos = pre.solve(torch.tensor(B, device=DEV), restart=c["restart"], rtol=c["rtol"])
+        torch.cuda.synchronize()
+        Xh = X.cpu().numpy()
+    finally:
+        pre.close()
+    assert all(i.status == 0 for i in infos)
+    S = A.to_scipy()
+    Rr = B - S @ Xh
+    rows = np.diff(sys_ptr)
+    for s in range(nsys):
+        s0, s1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
+        rel = np.linalg.norm(Rr[s0:s1], axis=0) / np.linalg.norm(B[s0:s1], axis=0)
+        assert rel.max() <= c["rtol"] * (1 + 1e-6), (s, rel.max())
+        for q in range(R):
+            assert abs(infos[s * R + q].true_relres - rel[q]) <= 1e-3 * c["rtol"]
+    order = np.argsort(rows, kind="stable")
+    for s in [int(v) for v in order[:4]] + [int(order[nsys // 6])]:
+        s0, s1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
+        As = Csr.from_scipy(S[s0:s1, s0:s1])
+        L, U = oracle.ilu0(As)
+        ML, MU = oracle.sait_thr(L, c["tau"], c["m"]), oracle.sait_thr(U, c["tau"], c["m"])
+        for q in range(R):
+            ref = oracle.gmres(As, B[s0:s1, q], ("sait64", ML, MU), restart=c["restart"], rtol=c["rtol"])
+            assert abs(infos[s * R + q].iterations - ref["iters"]) <= 1, (s, q, infos[s * R + q].iterations,
+                                                                          ref["iters"])
