@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 256-system solve")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched solve and print its record (for profiling that launch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -231,6 +233,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.batched_only:
+        print(json.dumps({"batched": batched_solve(torch, dev)}), flush=True)
+        return
     s = args.grid
     A = poisson3d(s) if s != 128 else config("c3")["A"]
     n = A.n
