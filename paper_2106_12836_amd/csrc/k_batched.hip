@@ -175,15 +175,17 @@ template <int RP> __device__ __forceinline__ double wave_sum_by_col(double x) {
     return x;
 }
 
-// Column indices and values of one 4-entry group of a lane's row (16-byte
-// aligned: slices start at multiples of 256 entries); streamed once, so
-// loaded non-temporally.
-__device__ __forceinline__ void load_group(const SellView &M, int64_t off, int (&cols)[4], double (&vals)[4]) {
+// Column indices and values of lane l's entries in the 4-entry group that
+// starts at grp (a multiple of 256: 16-byte aligned).  Indices: the lane's
+// four together; FP64 values: two planes, entries 0-1 of the 64 lanes then
+// entries 2-3.  Streamed once, so loaded non-temporally.
+__device__ __forceinline__ void load_group(const SellView &M, int64_t grp, int l, int (&cols)[4],
+                                           double (&vals)[4]) {
     typedef int i32x4 __attribute__((ext_vector_type(4)));
     typedef double f64x2 __attribute__((ext_vector_type(2)));
-    const i32x4 c = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(M.sci + off));
-    const f64x2 v0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(M.sv + off));
-    const f64x2 v1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(M.sv + off + 2));
+    const i32x4 c = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(M.sci + grp + 4 * l));
+    const f64x2 v0 = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(M.sv + grp + 2 * l));
+    const f64x2 v1 = __builtin_nontemporal_load(reinterpret_cast<const f64x2 *>(M.sv + grp + 128 + 2 * l));
     cols[0] = c.x;
     cols[1] = c.y;
     cols[2] = c.z;
@@ -230,11 +232,11 @@ __device__ __forceinline__ void phase_spmm(const BatchArgs &a, const SellView &M
         // flight while the rows of x for group gi are gathered
         int cols[4] = {0, 0, 0, 0};
         double vals[4] = {0.0, 0.0, 0.0, 0.0};
-        if (ngroups > 0) load_group(M, base + 4 * l, cols, vals);
+        if (ngroups > 0) load_group(M, base, l, cols, vals);
         for (int gi = 0; gi < ngroups; ++gi) {
             int nc[4] = {0, 0, 0, 0};
             double nv[4] = {0.0, 0.0, 0.0, 0.0};
-            if (gi + 1 < ngroups) load_group(M, base + (int64_t)(gi + 1) * 256 + 4 * l, nc, nv);
+            if (gi + 1 < ngroups) load_group(M, base + (int64_t)(gi + 1) * 256, l, nc, nv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (gi * 4 + j < len) {

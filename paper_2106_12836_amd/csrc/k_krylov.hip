@@ -4,15 +4,15 @@
 // comp(M_L, M_U) plus "othercomp": an operator product, inner products and
 // vector updates).
 //
-// Everything is FP64 and stays on the device: the Krylov basis V (and Z
-// for FGMRES), the inner products, the Hessenberg matrix with its Givens
-// rotations and the true residual.  One Arnoldi step is
-//   z_j = M v_j                      (SAIT apply, any storage precision)
-//   w   = A z_j                      (written straight into V[j+1])
-//   h   = V_j^T w,  w -= V_j h        classical Gram-Schmidt
-//   (repeated once if ||w_new|| < ||w_old|| / sqrt(2): the DGKS test)
-//   h_{j+1,j} = ||w||, Givens update of the least-squares residual
-//   v_{j+1} = w / h_{j+1,j}
+// Everything is FP64 and stays on the device: the Krylov basis V (and the
+// preconditioned vectors for FGMRES), the inner products, the Hessenberg
+// matrix with its Givens rotations and the true residual.  The Arnoldi
+// process is classical Gram-Schmidt with delayed re-orthogonalisation
+// (dcgs2_finalize): one step is
+//   z = M u_j, w = A z                    (SAIT apply, any storage precision)
+//   one pass: V^T u, V^T w, u.u, u.w      (k_dots2; the last block completes
+//                                          column j-1 and the coefficients)
+//   one pass: q_j and u_{j+1}             (k_update2)
 // Reductions are deterministic: each block writes a partial, the last block
 // to finish (atomic ticket) sums the partials in a fixed order.  Every
 // kernel of an Arnoldi step starts by reading the `done` flag, so steps
@@ -92,139 +92,263 @@ __device__ __forceinline__ Rows block_rows(int64_t n, int B) {
     return {lo, lo + chunk < n ? lo + chunk : n};
 }
 
-// Givens update of column j and the convergence decision (one thread).
-__device__ void finalize_step(GmresDev *st, double hn, bool use_h2, Mailbox *mb) {
-    const int k = st->restart;
-    const int j = st->jc;
-    double *H = st->H + (size_t)j * (k + 1);  // column j, (k+1) entries
-    for (int i = 0; i <= j; ++i) H[i] = use_h2 ? st->h1[i] + st->h2[i] : st->h1[i];
-    H[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double a = H[i], b = H[i + 1];
-        H[i] = st->cs[i] * a + st->sn[i] * b;
-        H[i + 1] = -st->sn[i] * a + st->cs[i] * b;
+// One Arnoldi step in delayed classical Gram-Schmidt form.  V_j holds u_j,
+// the once-projected (unnormalised) candidate for basis vector j; z = M u_j
+// and w = A z are in hand.  One pass over the basis gives
+//   a = Q^T u, b = Q^T w (Q = V_0 .. V_{j-1}), c = u.u, d = u.w,
+// then (one block):
+//   rho = ||u - Q a|| = sqrt(c - a.a)                 (beta at j = 0)
+//   column j-1 of the Hessenberg matrix: s1 + a over rows < j, rho at row j,
+//   its Givens rotation, the residual estimate and the stop decision;
+//   e = q_j . w = (d - a.b) / rho, and from the Arnoldi relation
+//   A M Q = Q_j H the first projection of column j, s1 = ([b; e] - H a) / rho;
+// and the update pass writes
+//   q_j = (u - Q a) / rho,   u_{j+1} = (w - (e/rho) u - Q (b - (e/rho) a)) / rho.
+// FGMRES keeps z~_j = M u_j: with z_j the vectors that satisfy A Z = Q_{j+1} H,
+// z~_j = sum_{i<j} a_i z_i + rho z_j, i.e. Z~ = Z Gamma with Gamma upper
+// triangular (column j: a, rho), so the cycle's update is x += Z~ (Gamma^-1 y).
+// Step j = k only completes column k-1.
+__device__ void dcgs2_finalize(GmresDev *st, int j, bool full, Mailbox *mb, double *sh) {
+    const int k = st->restart, K1 = k + 1;
+    const double *red = st->red;
+    const double c = red[2 * k], d = red[2 * k + 1];
+    __shared__ double rho_s, e_s;
+    __shared__ int stop_s;
+    // a.a and a.b over the block (fixed order)
+    double aa = 0.0, ab = 0.0;
+    for (int i = threadIdx.x; i < j; i += kNT) {
+        aa = fma(red[i], red[i], aa);
+        if (full) ab = fma(red[i], red[k + i], ab);
     }
-    const double a = H[j], b = H[j + 1];
-    const double den = hypot(a, b);
-    double c = 1.0, s = 0.0;
-    if (den != 0.0) {
-        c = a / den;
-        s = b / den;
-    }
-    st->cs[j] = c;
-    st->sn[j] = s;
-    H[j] = den;
-    H[j + 1] = 0.0;
-    st->g[j + 1] = -s * st->g[j];
-    st->g[j] = c * st->g[j];
-    st->jc = j + 1;
-    st->iters += 1;
-    st->est = fabs(st->g[j + 1]) / st->nb;
-    st->inv_hn = hn != 0.0 ? 1.0 / hn : 0.0;
-    const bool stop = st->est <= st->rtol || st->iters >= st->maxit || hn == 0.0 || st->jc >= k;
-    st->done = stop ? 1 : 0;
-    if (mb) {
-        mb->est = st->est;
-        mb->iters = st->iters;
-        __threadfence_system();
-        __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-}
-
-// h[i] = V_i . w for i < nv (grouped by 4), optionally also w . w.
-__global__ __launch_bounds__(kNT) void k_dots(int64_t n, const double *__restrict__ V, int64_t ldv, int nv,
-                                              const double *__restrict__ w, GmresDev *st, int phase, double *part,
-                                              unsigned *counter) {
-    __shared__ double sh[4];
-    if (st->done) return;
-    if (phase == 2 && !st->reorth) return;
-    const int B = gridDim.x;
-    const Rows R = block_rows(n, B);
-    for (int i0 = 0; i0 < nv; i0 += 4) {
-        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        const double *v0 = V + (int64_t)i0 * ldv;
-        const int m = nv - i0;
-        for (int64_t r = R.lo + threadIdx.x; r < R.hi; r += kNT) {
-            const double x = w[r];
-            a0 = fma(v0[r], x, a0);
-            if (m > 1) a1 = fma(v0[ldv + r], x, a1);
-            if (m > 2) a2 = fma(v0[2 * ldv + r], x, a2);
-            if (m > 3) a3 = fma(v0[3 * ldv + r], x, a3);
-        }
-        const double s0 = block_sum(a0, sh);
-        const double s1 = m > 1 ? block_sum(a1, sh) : 0.0;
-        const double s2 = m > 2 ? block_sum(a2, sh) : 0.0;
-        const double s3 = m > 3 ? block_sum(a3, sh) : 0.0;
-        if (threadIdx.x == 0) {
-            part[(size_t)i0 * B + blockIdx.x] = s0;
-            if (m > 1) part[(size_t)(i0 + 1) * B + blockIdx.x] = s1;
-            if (m > 2) part[(size_t)(i0 + 2) * B + blockIdx.x] = s2;
-            if (m > 3) part[(size_t)(i0 + 3) * B + blockIdx.x] = s3;
-        }
-    }
-    const bool with_norm = phase == 1;
-    if (with_norm) {
-        double a = 0;
-        for (int64_t r = R.lo + threadIdx.x; r < R.hi; r += kNT) a = fma(w[r], w[r], a);
-        const double s = block_sum(a, sh);
-        if (threadIdx.x == 0) part[(size_t)nv * B + blockIdx.x] = s;
-    }
-    if (!last_block(counter)) return;
-    double *out = phase == 1 ? st->h1 : st->h2;
-    reduce_partials(part, B, nv, out, sh);
-    if (with_norm) reduce_partials(part + (size_t)nv * B, B, 1, &st->wpre2, sh);
-    if (threadIdx.x == 0) *counter = 0;
-}
-
-// w -= sum_i h_i V_i for i < nv, then ||w||^2; last block decides
-// reorthogonalisation (phase 1) or finalises the step.
-__global__ __launch_bounds__(kNT) void k_update(int64_t n, const double *__restrict__ V, int64_t ldv, int nv,
-                                                double *__restrict__ w, GmresDev *st, int phase, double *part,
-                                                unsigned *counter, Mailbox *mb) {
-    __shared__ double sh[4];
-    __shared__ double hs[64];
-    if (st->done) return;
-    if (phase == 2 && !st->reorth) return;
-    const double *h = phase == 1 ? st->h1 : st->h2;
-    const int B = gridDim.x;
-    const Rows R = block_rows(n, B);
-    double nrm = 0;
-    for (int i0 = 0; i0 < nv; i0 += 64) {
-        const int m = nv - i0 < 64 ? nv - i0 : 64;
-        __syncthreads();
-        if (threadIdx.x < m) hs[threadIdx.x] = h[i0 + threadIdx.x];
-        __syncthreads();
-        const bool final_chunk = i0 + 64 >= nv;
-        for (int64_t r = R.lo + threadIdx.x; r < R.hi; r += kNT) {
-            double x = w[r];
-            const double *vp = V + (int64_t)i0 * ldv + r;
-            for (int i = 0; i < m; ++i) x = fma(-hs[i], vp[(int64_t)i * ldv], x);
-            w[r] = x;
-            if (final_chunk) nrm = fma(x, x, nrm);
-        }
-    }
-    const double s = block_sum(nrm, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (!last_block(counter)) return;
-    double hn2 = 0;
-    reduce_partials(part, B, 1, &hn2, sh);
+    aa = block_sum(aa, sh);
+    ab = block_sum(ab, sh);
     if (threadIdx.x == 0) {
-        *counter = 0;
-        if (phase == 1 && hn2 < 0.5 * st->wpre2) {
-            st->reorth = 1;  // DGKS: too much cancellation, orthogonalise again
-        } else {
-            finalize_step(st, sqrt(hn2), phase == 2, mb);
-            st->reorth = 0;
+        double rho = st->beta;
+        if (j > 0) {
+            const double r2 = c - aa;
+            rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+        }
+        rho_s = rho;
+        e_s = (full && rho != 0.0) ? (d - ab) / rho : 0.0;
+        stop_s = 0;
+    }
+    __syncthreads();
+    const double rho = rho_s;
+    if (j > 0) {
+        double *Hc = st->Hraw + (size_t)(j - 1) * K1;
+        for (int i = threadIdx.x; i < j; i += kNT) Hc[i] = st->s1[i] + red[i];
+        if (threadIdx.x == 0) Hc[j] = rho;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double *Rc = st->R + (size_t)(j - 1) * K1;
+            for (int i = 0; i <= j; ++i) Rc[i] = Hc[i];
+            for (int i = 0; i + 1 < j; ++i) {
+                const double x0 = Rc[i], x1 = Rc[i + 1];
+                Rc[i] = st->cs[i] * x0 + st->sn[i] * x1;
+                Rc[i + 1] = -st->sn[i] * x0 + st->cs[i] * x1;
+            }
+            const double x0 = Rc[j - 1], x1 = Rc[j];
+            const double den = hypot(x0, x1);
+            double cc = 1.0, ss = 0.0;
+            if (den != 0.0) {
+                cc = x0 / den;
+                ss = x1 / den;
+            }
+            st->cs[j - 1] = cc;
+            st->sn[j - 1] = ss;
+            Rc[j - 1] = den;
+            Rc[j] = 0.0;
+            st->g[j] = -ss * st->g[j - 1];
+            st->g[j - 1] = cc * st->g[j - 1];
+            st->jc = j;
+            st->iters += 1;
+            st->est = fabs(st->g[j]) / st->nb;
+            const bool stop = st->est <= st->rtol || st->iters >= st->maxit || rho == 0.0 || !full;
+            stop_s = stop ? 1 : 0;
+            st->done = stop_s;
+            if (mb) {
+                mb->est = st->est;
+                mb->iters = st->iters;
+                __threadfence_system();
+                __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        __syncthreads();
+        if (stop_s) return;
+    }
+    // coefficients of step j (j < k here)
+    const double e = e_s, eor = e / rho;
+    for (int i = threadIdx.x; i <= j; i += kNT) {
+        double ha = 0.0;  // (H a)_i over the completed columns m < j (column m has rows <= m+1)
+        for (int m = (i > 0 ? i - 1 : 0); m < j; ++m) ha = fma(st->Hraw[(size_t)m * K1 + i], red[m], ha);
+        const double bz = i < j ? red[k + i] : e;
+        st->s1n[i] = (bz - ha) / rho;
+    }
+    for (int i = threadIdx.x; i < j; i += kNT) {
+        st->ca[i] = red[i];
+        st->cg[i] = red[k + i] - eor * red[i];
+    }
+    if (st->Gam) {
+        double *Gc = st->Gam + (size_t)j * k;
+        for (int i = threadIdx.x; i < j; i += kNT) Gc[i] = red[i];
+        if (threadIdx.x == 0) Gc[j] = rho;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += kNT) st->s1[i] = st->s1n[i];
+    if (threadIdx.x == 0) {
+        st->rinv = 1.0 / rho;
+        st->eor = eor;
+    }
+}
+
+// One sweep of the inner-product pass over rows [lo, hi) of this thread:
+// C basis vectors (vp), u, w (may be null), and u.u, u.w on the first sweep.
+template <int C>
+__device__ __forceinline__ void dots_rows(const double *const (&vp)[8], const double *u, const double *w, int64_t lo,
+                                          int64_t hi, bool first, double (&av)[8], double (&bv)[8], double &cu,
+                                          double &du) {
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kNT) {
+        const double ue = u[r];
+        const double we = w ? w[r] : 0.0;
+        if (first) {
+            cu = fma(ue, ue, cu);
+            du = fma(ue, we, du);
+        }
+        double qv[C > 0 ? C : 1];
+#pragma unroll
+        for (int c = 0; c < C; ++c) qv[c] = vp[c][r];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            av[c] = fma(qv[c], ue, av[c]);
+            bv[c] = fma(qv[c], we, bv[c]);
         }
     }
 }
 
-// V[j+1] = w * (1/h_{j+1,j})  (in place; skipped once the cycle is done)
-__global__ void k_normalize(int64_t n, double *__restrict__ w, const GmresDev *st) {
+// Partial inner products of one Arnoldi step (nq = j basis vectors, u = V_j,
+// w = A M u_j or null at the closing step), per block into part[idx * B +
+// block] with idx = i (V_i.u), k + i (V_i.w), 2k (u.u), 2k + 1 (u.w); the
+// last block to finish sums them in block order and runs dcgs2_finalize.
+__global__ __launch_bounds__(kNT) void k_dots2(int64_t n, const double *__restrict__ V, int64_t ldv, int nq,
+                                               const double *__restrict__ u, const double *__restrict__ w,
+                                               GmresDev *st, double *part, unsigned *counter, Mailbox *mb) {
+    constexpr int kSl = 18;
+    __shared__ double sh[4 * kSl];
     if (st->done) return;
-    const double s = st->inv_hn;
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-        w[r] *= s;
+    const int k = st->restart;
+    const int B = gridDim.x;
+    const Rows Rw = block_rows(n, B);
+    const int nch = nq > 0 ? (nq + 7) / 8 : 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int i0 = ch * 8;
+        const int cnt = nq - i0 < 8 ? nq - i0 : 8;
+        const double *vp[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) vp[c] = V + (int64_t)(i0 + c < nq ? i0 + c : (nq > 0 ? nq - 1 : 0)) * ldv;
+        double av[8], bv[8], cu = 0.0, du = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) av[c] = bv[c] = 0.0;
+        switch (cnt <= 0 ? 0 : (cnt + 3) >> 2) {
+        case 0: dots_rows<0>(vp, u, w, Rw.lo, Rw.hi, ch == 0, av, bv, cu, du); break;
+        case 1: dots_rows<4>(vp, u, w, Rw.lo, Rw.hi, ch == 0, av, bv, cu, du); break;
+        default: dots_rows<8>(vp, u, w, Rw.lo, Rw.hi, ch == 0, av, bv, cu, du); break;
+        }
+#pragma unroll
+        for (int sl = 0; sl < kSl; ++sl) {
+            const double v = sl < 8 ? av[sl] : sl < 16 ? bv[sl - 8] : sl == 16 ? cu : du;
+            const double t = wave_sum(v);
+            if (lane == 0) sh[wv * kSl + sl] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < kSl) {
+            const int sl = threadIdx.x;
+            int idx = -1;
+            if (sl < 8) {
+                if (i0 + sl < nq) idx = i0 + sl;
+            } else if (sl < 16) {
+                if (w && i0 + sl - 8 < nq) idx = k + i0 + sl - 8;
+            } else if (ch == 0 && (sl == 16 || w)) {
+                idx = sl == 16 ? 2 * k : 2 * k + 1;
+            }
+            if (idx >= 0)
+                part[(size_t)idx * B + blockIdx.x] = (sh[sl] + sh[kSl + sl]) + (sh[2 * kSl + sl] + sh[3 * kSl + sl]);
+        }
+        __syncthreads();
+    }
+    if (!last_block(counter)) return;
+    // one wavefront per value: lanes take blocks, then a fixed butterfly
+    const int nvals = 2 * nq + 2;
+    for (int v = wv; v < nvals; v += kNT / 64) {
+        int idx;
+        if (v < nq) idx = v;
+        else if (v < 2 * nq) idx = k + v - nq;
+        else idx = v == 2 * nq ? 2 * k : 2 * k + 1;
+        if (!w && (idx == 2 * k + 1 || (idx >= k && idx < 2 * k))) continue;
+        double t = 0.0;
+        for (int b = lane; b < B; b += 64) t += ld_acq(part + (size_t)idx * B + b);
+        t = wave_sum(t);
+        if (lane == 0) st->red[idx] = t;
+    }
+    if (!w && threadIdx.x == 0) st->red[2 * k + 1] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) *counter = 0;
+    dcgs2_finalize(st, nq, w != nullptr, mb, sh);
+}
+
+// Update of step j (skipped once the cycle is done):
+//   V_j <- (u - sum_i ca_i V_i) / rho,   V_{j+1} <- (w - (e/rho) u - sum_i cg_i V_i) / rho
+// with u = V_j, w = V_{j+1} on entry, i < j; coefficients staged 64 at a time.
+__global__ __launch_bounds__(kNT) void k_update2(int64_t n, double *__restrict__ V, int64_t ldv, int j,
+                                                 const GmresDev *st) {
+    __shared__ double ca[64], cg[64];
+    if (st->done) return;
+    const double ri = st->rinv, eo = st->eor;
+    double *uv = V + (int64_t)j * ldv, *wv = V + (int64_t)(j + 1) * ldv;
+    const int B = gridDim.x;
+    const Rows Rw = block_rows(n, B);
+    const int nch = j > 0 ? (j + 63) / 64 : 1;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int i0 = ch * 64;
+        const int m = j - i0 < 64 ? j - i0 : 64;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            ca[threadIdx.x] = threadIdx.x < m ? st->ca[i0 + threadIdx.x] : 0.0;
+            cg[threadIdx.x] = threadIdx.x < m ? st->cg[i0 + threadIdx.x] : 0.0;
+        }
+        __syncthreads();
+        const bool first = ch == 0, last = ch == nch - 1;
+        const double *Q = V + (int64_t)i0 * ldv;
+        for (int64_t r = Rw.lo + threadIdx.x; r < Rw.hi; r += kNT) {
+            const double ue = uv[r];
+            double we = wv[r];
+            if (first) we = fma(-eo, ue, we);
+            double sa = 0.0, sg = 0.0;
+            int i = 0;
+            for (; i + 8 <= m; i += 8) {
+                double q[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) q[c] = Q[(int64_t)(i + c) * ldv + r];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    sa = fma(ca[i + c], q[c], sa);
+                    sg = fma(cg[i + c], q[c], sg);
+                }
+            }
+            for (; i < m; ++i) {
+                const double q = Q[(int64_t)i * ldv + r];
+                sa = fma(ca[i], q, sa);
+                sg = fma(cg[i], q, sg);
+            }
+            if (last) {
+                uv[r] = (ue - sa) * ri;
+                wv[r] = (we - sg) * ri;
+            } else {
+                uv[r] = ue - sa;
+                wv[r] = we - sg;
+            }
+        }
+    }
 }
 
 // ||r||^2 of the residual in V[0]; the last block starts a cycle:
@@ -252,8 +376,6 @@ __global__ __launch_bounds__(kNT) void k_cycle_norm(int64_t n, const double *__r
             st->g[0] = nrm;
             for (int i = 1; i <= st->restart; ++i) st->g[i] = 0.0;
             st->jc = 0;
-            st->reorth = 0;
-            st->inv_hn = nrm != 0.0 ? 1.0 / nrm : 0.0;
             const bool ok = st->nb == 0.0 || nrm / st->nb <= st->rtol;
             st->done = (ok || st->iters >= st->maxit) ? 1 : 0;
             if (mb) {
@@ -265,30 +387,39 @@ __global__ __launch_bounds__(kNT) void k_cycle_norm(int64_t n, const double *__r
     }
 }
 
-// y = R^-1 g over the jc completed steps (single block, sequential).
+// y = R^-1 g over the jc completed steps; for FGMRES also yh = Gamma^-1 y
+// (single thread, sequential back substitutions).
 __global__ void k_hsolve(GmresDev *st) {
     if (threadIdx.x != 0) return;
     const int k = st->restart, jc = st->jc;
     for (int i = jc - 1; i >= 0; --i) {
         double s = st->g[i];
-        for (int t = i + 1; t < jc; ++t) s -= st->H[(size_t)t * (k + 1) + i] * st->y[t];
-        const double d = st->H[(size_t)i * (k + 1) + i];
+        for (int t = i + 1; t < jc; ++t) s -= st->R[(size_t)t * (k + 1) + i] * st->y[t];
+        const double d = st->R[(size_t)i * (k + 1) + i];
         st->y[i] = d != 0.0 ? s / d : 0.0;
+    }
+    if (!st->Gam) return;
+    for (int i = jc - 1; i >= 0; --i) {
+        double s = st->y[i];
+        for (int t = i + 1; t < jc; ++t) s -= st->Gam[(size_t)t * k + i] * st->yh[t];
+        const double d = st->Gam[(size_t)i * k + i];
+        st->yh[i] = d != 0.0 ? s / d : 0.0;
     }
 }
 
-// out (+)= sum_{i < jc} y_i B_i
+// out (+)= sum_{i < jc} c_i B_i with c = y (GMRES) or yh (FGMRES)
 __global__ void k_combine(int64_t n, const double *__restrict__ Bv, int64_t ldb, const GmresDev *st,
                           double *__restrict__ out, int accumulate) {
     __shared__ double ys[64];
     const int jc = st->jc;
+    const double *yc = st->Gam ? st->yh : st->y;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r - threadIdx.x < n;
          r += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int i0 = 0; i0 < jc; i0 += 64) {
             const int m = jc - i0 < 64 ? jc - i0 : 64;
             __syncthreads();
-            if (threadIdx.x < m) ys[threadIdx.x] = st->y[i0 + threadIdx.x];
+            if (threadIdx.x < m) ys[threadIdx.x] = yc[i0 + threadIdx.x];
             __syncthreads();
             if (r < n)
                 for (int i = 0; i < m; ++i) acc = fma(ys[i], Bv[(int64_t)(i0 + i) * ldb + r], acc);
@@ -315,7 +446,6 @@ __global__ void k_init_state(GmresDev *st, int restart, int maxit, double rtol) 
     st->iters = 0;
     st->done = 0;
     st->jc = 0;
-    st->reorth = 0;
     st->nb = 0.0;
 }
 
@@ -341,10 +471,11 @@ Solver::~Solver() {
 
 void Solver::ensure(Allocator *a, int64_t n, int restart, bool flexible, int precision) {
     const int64_t ld = (n + 63) / 64 * 64;  // 512-byte aligned vectors
-    const bool need = n != n_ || restart != restart_ || (flexible && Z_.empty()) || (precision != SAIT_F64 && y32_.empty());
+    const bool need = n != n_ || restart != restart_ || flexible != flex_ || (precision != SAIT_F64 && y32_.empty());
     if (!need) return;
     n_ = n;
     restart_ = restart;
+    flex_ = flexible;
     ldv_ = ld;
     const int64_t nn = std::max<int64_t>(ld, 64);
     V_.alloc(a, (size_t)nn * (restart + 1) * sizeof(double));
@@ -354,28 +485,34 @@ void Solver::ensure(Allocator *a, int64_t n, int restart, bool flexible, int pre
     ut_.alloc(a, (size_t)nn * sizeof(double));
     if (precision != SAIT_F64) y32_.alloc(a, (size_t)nn * sizeof(float));
     else y32_.reset();
-    arr_.alloc(a, sizeof(double) * ((size_t)(restart + 1) * restart + 6 * (restart + 2)));
+    const size_t kk = (size_t)restart, hsz = (kk + 1) * kk;
+    arr_.alloc(a, sizeof(double) * (2 * hsz + (flexible ? kk * kk : 0) + 9 * (kk + 2) + 2 * kk + 2));
     st_.alloc(a, sizeof(GmresDev));
-    part_.alloc(a, sizeof(double) * (size_t)1024 * (restart + 3));
+    part_.alloc(a, sizeof(double) * (size_t)1024 * (2 * kk + 2));
     counters_.alloc(a, 4 * sizeof(unsigned));
     SAIT_HIP(hipMemset(counters_.as<void>(), 0, 4 * sizeof(unsigned)));
     if (!mailbox_) SAIT_HIP(hipHostMalloc(&mailbox_, 256, hipHostMallocMapped));
     // bind the array pointers inside the device state
     GmresDev h{};
     double *base = arr_.as<double>();
-    h.H = base;
-    base += (size_t)(restart + 1) * restart;
-    h.cs = base;
-    base += restart + 2;
-    h.sn = base;
-    base += restart + 2;
-    h.g = base;
-    base += restart + 2;
-    h.y = base;
-    base += restart + 2;
-    h.h1 = base;
-    base += restart + 2;
-    h.h2 = base;
+    auto take = [&](size_t cnt) {
+        double *r = base;
+        base += cnt;
+        return r;
+    };
+    h.Hraw = take(hsz);
+    h.R = take(hsz);
+    h.Gam = flexible ? take(kk * kk) : nullptr;
+    h.cs = take(kk + 2);
+    h.sn = take(kk + 2);
+    h.g = take(kk + 2);
+    h.y = take(kk + 2);
+    h.yh = take(kk + 2);
+    h.s1 = take(kk + 2);
+    h.s1n = take(kk + 2);
+    h.ca = take(kk + 2);
+    h.cg = take(kk + 2);
+    h.red = take(2 * kk + 2);
     SAIT_HIP(hipMemcpy(st_.as<void>(), &h, sizeof(h), hipMemcpyHostToDevice));
 }
 
@@ -439,25 +576,23 @@ int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, cons
             status = SAIT_NOT_CONVERGED;
             return status;
         }
-        hipLaunchKernelGGL(k_normalize, dim3(SB), dim3(256), 0, s, n, V, st);
-        SAIT_LAUNCH_CHECK();
-        // Arnoldi steps, a few queued ahead of the polled mailbox
+        // Arnoldi steps (step k closes column k-1), a few queued ahead of the
+        // polled mailbox
         constexpr int kAhead = 3;
         hipEvent_t ev[kAhead + 1];
         for (auto &e : ev) SAIT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         int enq = 0;
         bool stop = false;
-        for (int j = 0; j < k && !stop; ++j) {
-            double *vj = V + (int64_t)j * ldv_;
-            double *w = V + (int64_t)(j + 1) * ldv_;
-            double *zj = o.flexible ? Z_.as<double>() + (int64_t)j * ldv_ : ut_.as<double>();
-            apply_prec(ops, vj, zj, s);
-            spmv(*ops.A, zj, XKind::F64, w, YKind::F64, 1, 1, 1, ops.lanesA, s);
-            hipLaunchKernelGGL(k_dots, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j + 1, w, st, 1, part, cnt);
-            hipLaunchKernelGGL(k_update, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j + 1, w, st, 1, part, cnt + 1, mbd);
-            hipLaunchKernelGGL(k_dots, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j + 1, w, st, 2, part, cnt);
-            hipLaunchKernelGGL(k_update, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j + 1, w, st, 2, part, cnt + 1, mbd);
-            hipLaunchKernelGGL(k_normalize, dim3(SB), dim3(256), 0, s, n, w, st);
+        for (int j = 0; j <= k && !stop; ++j) {
+            double *uj = V + (int64_t)j * ldv_;
+            double *w = j < k ? V + (int64_t)(j + 1) * ldv_ : nullptr;
+            if (j < k) {
+                double *zj = o.flexible ? Z_.as<double>() + (int64_t)j * ldv_ : ut_.as<double>();
+                apply_prec(ops, uj, zj, s);
+                spmv(*ops.A, zj, XKind::F64, w, YKind::F64, 1, 1, 1, ops.lanesA, s);
+            }
+            hipLaunchKernelGGL(k_dots2, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j, uj, w, st, part, cnt, mbd);
+            if (j < k) hipLaunchKernelGGL(k_update2, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j, st);
             SAIT_LAUNCH_CHECK();
             SAIT_HIP(hipEventRecord(ev[j % (kAhead + 1)], s));
             ++enq;

@@ -90,8 +90,12 @@ __device__ __forceinline__ float add_rn(float a, float b) {
     return a + b;
 }
 
-// Four consecutive entries starting at a multiple of 4: 16-byte (8-byte for
-// bfloat16) aligned vector loads, streamed past the caches.
+// The four entries of one lane in one 4-entry group of a slice (grp = the
+// group's first element): 16-byte (8-byte for bfloat16) aligned vector
+// loads, streamed past the caches.  FP64 groups are stored as two planes --
+// entries 0-1 of the 64 lanes, then entries 2-3 -- so each of the two loads
+// of a wavefront reads 1 KiB contiguously; binary32 and bfloat16 groups hold
+// a lane's four entries together.
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -104,7 +108,8 @@ __device__ __forceinline__ void load_idx4(const int *p, int (&o)[4]) {
     o[2] = a.z;
     o[3] = a.w;
 }
-__device__ __forceinline__ void load_quad(const double *p, double (&o)[4]) {
+// Four consecutive CSR entries starting at a multiple of 4.
+__device__ __forceinline__ void load_csr4(const double *p, double (&o)[4]) {
     const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p));
     const d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(p + 2));
     o[0] = a.x;
@@ -112,15 +117,38 @@ __device__ __forceinline__ void load_quad(const double *p, double (&o)[4]) {
     o[2] = b.x;
     o[3] = b.y;
 }
-__device__ __forceinline__ void load_quad(const float *p, float (&o)[4]) {
+__device__ __forceinline__ void load_csr4(const float *p, float (&o)[4]) {
     const f4v a = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p));
     o[0] = a.x;
     o[1] = a.y;
     o[2] = a.z;
     o[3] = a.w;
 }
-__device__ __forceinline__ void load_quad(const Bf16 *p, float (&o)[4]) {
+__device__ __forceinline__ void load_csr4(const Bf16 *p, float (&o)[4]) {
     const u4v a = __builtin_nontemporal_load(reinterpret_cast<const u4v *>(p));
+    o[0] = __uint_as_float(((unsigned)a.x) << 16);
+    o[1] = __uint_as_float(((unsigned)a.y) << 16);
+    o[2] = __uint_as_float(((unsigned)a.z) << 16);
+    o[3] = __uint_as_float(((unsigned)a.w) << 16);
+}
+
+__device__ __forceinline__ void load_quad(const double *grp, int l, double (&o)[4]) {
+    const d2v a = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(grp + 2 * l));
+    const d2v b = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(grp + 128 + 2 * l));
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ __forceinline__ void load_quad(const float *grp, int l, float (&o)[4]) {
+    const f4v a = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(grp + 4 * l));
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+}
+__device__ __forceinline__ void load_quad(const Bf16 *grp, int l, float (&o)[4]) {
+    const u4v a = __builtin_nontemporal_load(reinterpret_cast<const u4v *>(grp + 4 * l));
     o[0] = __uint_as_float(((unsigned)a.x) << 16);
     o[1] = __uint_as_float(((unsigned)a.y) << 16);
     o[2] = __uint_as_float(((unsigned)a.z) << 16);
@@ -157,9 +185,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(int n, int nslices, const 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (g0 + u < ngroups) {
-                const int64_t off = base + (int64_t)(g0 + u) * 256 + 4 * l;
-                load_idx4(sci + off, cols[slot][u]);
-                load_quad(sv + off, vals[slot][u]);
+                const int64_t grp = base + (int64_t)(g0 + u) * 256;
+                load_idx4(sci + grp + 4 * l, cols[slot][u]);
+                load_quad(sv + grp, l, vals[slot][u]);
             }
         }
     };
@@ -201,6 +229,13 @@ __global__ void k_sell_width(int n, int nslices, const int *__restrict__ rp, int
     if (l == 0) cnt[s] = (int64_t)64 * ((len + 3) & ~3);
 }
 
+// Position of entry k of lane l's row in the value array of a group that
+// starts at grp (see load_quad).
+template <class VT> __device__ __forceinline__ int64_t sell_value_index(int64_t grp, int l, int k) {
+    if constexpr (sizeof(VT) == 8) return grp + ((k >> 1) & 1) * 128 + 2 * l + (k & 1);
+    else return grp + 4 * l + (k & 3);
+}
+
 template <class VT>
 __global__ void k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ ci, const VT *__restrict__ v,
                             const int64_t *__restrict__ sptr, int *__restrict__ sci, VT *__restrict__ sv) {
@@ -213,13 +248,15 @@ __global__ void k_sell_fill(int n, const int *__restrict__ rp, const int *__rest
     const int b0 = row < n ? rp[row] : 0;
     const int len = row < n ? rp[row + 1] - b0 : 0;
     for (int k = 0; k < width; ++k) {
-        const int64_t off = base + (int64_t)(k >> 2) * 256 + 4 * l + (k & 3);
+        const int64_t grp = base + (int64_t)(k >> 2) * 256;
+        const int64_t off = grp + 4 * l + (k & 3);
+        const int64_t voff = sell_value_index<VT>(grp, l, k);
         if (k < len) {
             sci[off] = ci[b0 + k];
-            sv[off] = v[b0 + k];
+            sv[voff] = v[b0 + k];
         } else {
             sci[off] = 0;
-            sv[off] = VT{};
+            sv[voff] = VT{};
         }
     }
 }
@@ -263,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(const int *__restrict__ 
             const int base = a0 + 4 * (k * kBlock + t);
             if (base < c1) {
                 load_idx4(ci + base, cols[k]);
-                load_quad(v + base, vals[k]);
+                load_csr4(v + base, vals[k]);
             }
         }
 #pragma unroll

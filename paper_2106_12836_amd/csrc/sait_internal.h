@@ -95,10 +95,13 @@ struct DevCsr {
     int64_t nblk[2] = {0, 0};
     // Sliced-ELL copy for the one-row-per-lane kernel: slice s holds rows
     // 64 s .. 64 s + 63 (one wavefront), padded to the slice's longest row
-    // rounded up to a multiple of 4; entry k of row 64 s + l is stored at
-    // sell_ptr[s] + (k / 4) * 256 + 4 l + k % 4.  Padding holds column 0 and
-    // value 0 and is never used (row lengths come from rp).  Values are in
-    // the storage precision.
+    // rounded up to a multiple of 4, in groups of 4 entries per row (256 per
+    // group).  With g = sell_ptr[s] + (k / 4) * 256, the column of entry k of
+    // row 64 s + l is at g + 4 l + k % 4; its value at the same place for
+    // binary32 / bfloat16 storage, and at g + 128 ((k / 2) % 2) + 2 l + k % 2
+    // for FP64 (two planes per group).  Padding holds column 0 and value 0
+    // and is never used (row lengths come from rp).  Values are in the
+    // storage precision.
     DevBuf sell_ptr, sell_ci, sell_v;
     int64_t nslices = 0, sell_nnz = 0;
     const void *stored() const { return precision == SAIT_F64 ? v.as<void>() : vs.as<void>(); }

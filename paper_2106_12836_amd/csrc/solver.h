@@ -7,10 +7,12 @@ namespace sait {
 
 // Lives in device memory; the array pointers point into one device buffer.
 struct GmresDev {
-    double *H;    // (restart+1) x restart Hessenberg / R factor, column-major
-    double *cs, *sn, *g, *y, *h1, *h2;
-    double nb, beta, est, inv_hn, wpre2, rtol;
-    int restart, maxit, iters, jc, done, reorth;
+    double *Hraw, *R;   // (restart+1) x restart, column-major: Arnoldi Hessenberg, and after the rotations
+    double *Gam;        // restart x restart, column-major (FGMRES): z~_j = sum_i Gam_ij z_i; null for GMRES
+    double *cs, *sn, *g, *y, *yh, *s1, *s1n, *ca, *cg;
+    double *red;        // 2 restart + 2 reduced inner products of the current step
+    double nb, beta, est, rinv, eor, rtol;
+    int restart, maxit, iters, jc, done;
 };
 
 // Operators of one solve: A (FP64) and the preconditioner z = M2 (M1 v).
@@ -36,6 +38,7 @@ class Solver {
 
     int64_t n_ = -1, ldv_ = 0;
     int restart_ = 0;
+    bool flex_ = false;
     DevBuf V_, Z_, zt_, ut_, y32_, arr_, st_, part_, counters_;
     void *mailbox_ = nullptr;
 };
