@@ -11,7 +11,10 @@ FP64 form -- is measured after the timed loop and reported in
 `time_to_residual`.  `batched` reports the batched workload (256 anisotropic
 2D systems x 8 right-hand sides, GMRES(30) to 1e-8, one persistent launch):
 wall time, systems/s, pair-iterations/s and the modelled bytes per second
-(batched_bytes).
+(batched_bytes).  `other_workloads`: FP64 apply GB/s on the random
+diagonally dominant matrices and on the 2D convection-diffusion factors
+(also after a cache-evicting write), and the forward / adjoint solve times
+of the differentiable 512^2 workload.
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -207,6 +210,92 @@ def batched_solve(torch, dev):
     return out
 
 
+def apply_rate(torch, dev, A, opts, cache_evict_mib=0, reps=50):
+    """FP64 apply of one workload: GB/s from HIP events around each apply
+    (inputs resident); with cache_evict_mib > 0 a write of that many MiB
+    precedes every timed apply, so the factors come from HBM rather than the
+    256 MB last-level cache."""
+    from paper_2106_12836_amd import SaitPreconditioner, sait_time_apply
+    from workloads import uniform_vector
+
+    t0 = time.time()
+    pre = SaitPreconditioner(A, **opts)
+    torch.cuda.synchronize()
+    t_build = time.time() - t0
+    pre.autotune()
+    q = pre.query()
+    r = torch.tensor(uniform_vector(A.n, 11), dtype=torch.float64, device=dev)
+    z = torch.empty_like(r)
+    B = apply_bytes(A.n, q["nnz_ML"], q["nnz_MU"], "f64")
+    out = dict(n=A.n, nnz_A=A.nnz, nnz_ML=q["nnz_ML"], nnz_MU=q["nnz_MU"], bytes_apply=B, build_s=round(t_build, 3))
+    _, _, ms = sait_time_apply(pre.handle, r, z, reps=reps)
+    out["gbs_apply"] = round(B / (ms * 1e-3) / 1e9, 1)
+    out["pct_hbm_peak"] = round(100 * out["gbs_apply"] / HBM_PEAK_GBS, 1)
+    if cache_evict_mib:
+        scratch = torch.empty(cache_evict_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for i in range(reps):
+            scratch.fill_(float(i))
+            e0.record()
+            pre.apply(r, z)
+            e1.record()
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1)
+        out["gbs_apply_after_cache_evict"] = round(B / (tot / reps * 1e-3) / 1e9, 1)
+        out["cache_evict_mib"] = cache_evict_mib
+        del scratch
+    pre.close()
+    return out
+
+
+def extra_workloads(torch, dev):
+    """Apply throughput on the random diagonally dominant matrices (banded and
+    scattered columns) and on the 2D convection-diffusion factors, and the
+    forward + adjoint solve time of the differentiable workload."""
+    from paper_2106_12836_amd import SaitPreconditioner
+    from paper_2106_12836_amd.autograd import sait_solve_autograd
+    from workloads import config
+
+    out = {}
+    for name in ("rdd-b", "rdd-s"):
+        c = config(name)
+        out[name] = apply_rate(torch, dev, c["A"], dict(m=c["m"], tau=c["tau"]))
+        out[name]["workload"] = (f"random diagonally dominant n=2^22, 8 off-diagonals "
+                                 f"{'within +-2^14' if name == 'rdd-b' else 'anywhere'}, ILU(0) + SAIT_Thr(1e-2, 3)")
+        print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+    c = config("c2")
+    out["c2"] = apply_rate(torch, dev, c["A"], dict(ilu_kind=1, ilut_tau=c["ilut_tau"], ilut_fill=c["ilut_fill"],
+                                                   m=c["m"], tau=c["tau"]), cache_evict_mib=512)
+    out["c2"]["workload"] = "2D upwind convection-diffusion 1024^2, Pe = 10, ILUT(1e-3, 10) + SAIT_Thr(1e-3, 4)"
+    print(f"[bench] c2: {out['c2']}", file=sys.stderr, flush=True)
+    # differentiable workload: forward FGMRES + adjoint FGMRES + gradient, 512^2
+    c = config("c5")
+    A, At_, b = c["A"], c["A_target"], c["b"]
+    pre = SaitPreconditioner(A, m=c["m"], tau=c["tau"], build_transpose=1)
+    xt = torch.zeros(A.n, dtype=torch.float64, device=dev)  # the loss's target only shapes the adjoint rhs
+    times = []
+    for _ in range(2):
+        vals = torch.tensor(A.v, dtype=torch.float64, device=dev, requires_grad=True)
+        bt = torch.tensor(b, dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = sait_solve_autograd(vals, bt, pre, restart=c["restart"], rtol=c["rtol"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ((x - xt) ** 2).sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    pre.close()
+    out["c5"] = dict(workload="2D GRF diffusion 512^2 (n=262144), ILU(0) + SAIT_Thr(1e-2, 3), FGMRES(30) to 1e-12; "
+                              "backward = adjoint FGMRES on A^T with transposed factors + gradient on A's pattern",
+                     forward_s=round(times[-1][0], 4), backward_s=round(times[-1][1], 4))
+    print(f"[bench] c5: {out['c5']}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +306,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 256-system solve")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (rdd, c2, c5)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched solve and print its record (for profiling that launch)")
     args = ap.parse_args()
@@ -330,6 +420,10 @@ def main():
         roof["copy_kernel_gbs"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
 
+    extra = None
+    if not args.no_extra:
+        extra = extra_workloads(torch, dev)
+
     batched = None
     if not args.no_batched:
         print("[bench] batched solve (256 systems x 8 RHS) ...", file=sys.stderr, flush=True)
@@ -366,6 +460,7 @@ def main():
         "apply_by_precision": apply_stats,
         "time_to_residual": ttr,
         "batched": batched,
+        "other_workloads": extra,
     }
     print(json.dumps(line), flush=True)
 
