@@ -5,7 +5,9 @@ on A with the SAIT preconditioner M_U M_L.  Backward (adjoint method):
 lambda solves A^T lambda = dl/dx by FGMRES on A^T preconditioned with the
 transposed factors, z = M_L^T (M_U^T r); then dl/db = lambda and
 dl/dA_ij = -lambda_i x_j on the stored pattern of A.  The preconditioner
-is not differentiated: at convergence x does not depend on it.
+is not differentiated: at convergence x does not depend on it.  The
+results of the last forward and adjoint solves are kept on the
+preconditioner (last_forward_info, last_adjoint_info).
 """
 
 from __future__ import annotations
@@ -27,6 +29,7 @@ class SaitSolve(torch.autograd.Function):
         ctx.vals = vals_c
         ctx.opts = (restart, maxit, rtol)
         ctx.info = info
+        pre.last_forward_info = info[0]
         ctx.save_for_backward(x)
         return x
 
@@ -39,6 +42,7 @@ class SaitSolve(torch.autograd.Function):
         lam, info = pre.solve(gx.detach().contiguous(), transpose=True, restart=restart, maxit=maxit, rtol=rtol,
                               flexible=True)
         ctx.backward_info = info
+        pre.last_adjoint_info = info[0]
         gvals = pre.grad_values(lam, x)
         return gvals, lam, None, None, None, None
 

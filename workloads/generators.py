@@ -274,7 +274,8 @@ def config(name: str, small: bool = False) -> dict:
     c4  256 anisotropic 2D systems (s ~ U{32..512}, seed 3), 8 RHS each
         (seed 4), ILU(0) + SAIT(1e-2, 3), GMRES(30), 1e-8
     c5  GRF diffusion 512^2 (seed 5), ILU(0) + SAIT(1e-2, 3), FGMRES(30),
-        1e-12, f = 1, target from a perturbed kappa (seed 6)
+        1e-10 (1e-12 at the small size), f = 1, target from a perturbed kappa
+        (seed 6)
 
     ``small=True`` shrinks the grid so the CPU oracle finishes in seconds
     while the structure (stencil, parameters) is unchanged.
@@ -308,8 +309,10 @@ def config(name: str, small: bool = False) -> dict:
         gp = gaussian_random_field(s, seed=6)
         g = gaussian_random_field(s, seed=5)
         A_t, _ = grf_diffusion2d(s, kappa_log=g + 0.1 * gp)
+        # the FP64 true-residual floor of the 512^2 problem is ~8e-12, so the
+        # full size solves to 1e-10
         return dict(A=A, A_target=A_t, b=np.ones(A.n), ilu="ilu0", m=3, tau=1e-2, restart=30,
-                    rtol=1e-12, flexible=True, fd_seed=7, fd_dirs=16)
+                    rtol=1e-12 if small else 1e-10, flexible=True, fd_seed=7, fd_dirs=16)
     if name in ("rdd-b", "rdd-s"):
         n = 2**14 if small else 2**22
         A = random_diag_dominant(n, 8, band=(2**10 if small else 2**14) if name == "rdd-b" else None, seed=8)
