@@ -36,6 +36,7 @@ class _Prec(C.Structure):
         ("kind", C.c_int),
         ("rp1", _i32p), ("ci1", _i32p), ("v1", _f64p), ("f1", _f32p),
         ("rp2", _i32p), ("ci2", _i32p), ("v2", _f64p), ("f2", _f32p),
+        ("sweeps", C.c_int),
     ]
 
 
@@ -73,6 +74,9 @@ def lib():
         L.or_gmres.argtypes = [I64, _i32p, _i32p, _f64p, C.POINTER(_Prec), _f64p, _f64p,
                                C.c_int, C.c_int, D, C.c_int,
                                C.POINTER(C.c_int), C.POINTER(C.c_int), _f64p, _f64p, _f64p]
+        L.or_jacobi_sweeps.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, C.c_int, _f64p]
+        L.or_pcg.argtypes = [I64, _i32p, _i32p, _f64p, C.POINTER(_Prec), _f64p, _f64p, C.c_int, D,
+                             C.POINTER(C.c_int), C.POINTER(C.c_double), _f64p]
         L.or_free.argtypes = [C.c_void_p]
         L.or_free.restype = None
         L.or_num_threads.restype = C.c_int
@@ -264,31 +268,25 @@ def grad_values(A: Csr, lam, x):
     return g
 
 
-PREC_NONE, PREC_SAIT64, PREC_SAIT32, PREC_EXACT = 0, 1, 2, 3
+PREC_NONE, PREC_SAIT64, PREC_SAIT32, PREC_EXACT, PREC_JACOBI = 0, 1, 2, 3, 4
 
 
-def gmres(A: Csr, b, prec=None, x0=None, restart=30, maxit=10000, rtol=1e-8, flexible=False,
-          history=False):
-    """Restarted right-preconditioned (F)GMRES.
-
-    prec: None | ("sait64", M1, M2) | ("sait32", M1, f1, M2, f2) | ("exact", L, U)
-    where the preconditioner is z = M2 (M1 r) (for "exact": U^-1 (L^-1 r)).
-    Returns dict(x, iters, restarts, relres, est, status[, hist]).
-    """
-    keep, (rp, ci, v) = _csr_args(A)
-    b = np.ascontiguousarray(b, dtype=np.float64)
-    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
+def _make_prec(prec):
+    """or_prec for None | ("sait64", M1, M2) | ("sait32", M1, f1, M2, f2) |
+    ("exact", L, U) | ("jacobi", L, U, sweeps); returns (struct, arrays to keep alive)."""
     P = _Prec()
     hold = []
     if prec is None:
         P.kind = PREC_NONE
-    elif prec[0] in ("sait64", "exact"):
-        P.kind = PREC_SAIT64 if prec[0] == "sait64" else PREC_EXACT
+    elif prec[0] in ("sait64", "exact", "jacobi"):
+        P.kind = {"sait64": PREC_SAIT64, "exact": PREC_EXACT, "jacobi": PREC_JACOBI}[prec[0]]
         k1, a1 = _csr_args(prec[1])
         k2, a2 = _csr_args(prec[2])
         hold += [k1, k2]
         P.rp1, P.ci1, P.v1 = a1
         P.rp2, P.ci2, P.v2 = a2
+        if prec[0] == "jacobi":
+            P.sweeps = int(prec[3])
     elif prec[0] == "sait32":
         P.kind = PREC_SAIT32
         M1, f1, M2, f2 = prec[1:]
@@ -301,6 +299,51 @@ def gmres(A: Csr, b, prec=None, x0=None, restart=30, maxit=10000, rtol=1e-8, fle
         P.rp2, P.ci2, P.f2 = _p(arrs[3], _i32p), _p(arrs[4], _i32p), _p(arrs[5], _f32p)
     else:
         raise ValueError(prec[0])
+    return P, hold
+
+
+def jacobi_sweeps(T: Csr, r, sweeps: int):
+    """s Jacobi sweeps from zero for the triangular system T y = r (lower or
+    upper): y_i <- (r_i - sum_{j != i} T_ij y_j) / T_ii from the previous iterate."""
+    keep, (rp, ci, v) = _csr_args(T)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    y = np.empty(T.n)
+    _check(lib().or_jacobi_sweeps(T.n, rp, ci, v, _p(r, _f64p), int(sweeps), _p(y, _f64p)), "jacobi_sweeps")
+    return y
+
+
+def pcg(A: Csr, b, prec=None, x0=None, maxit=10000, rtol=1e-10, history=False):
+    """Preconditioned conjugate gradients (textbook form), stopping on the
+    recursively updated relative residual; prec as for gmres.  Returns
+    dict(x, iters, relres (true, at the end), status[, hist])."""
+    keep, (rp, ci, v) = _csr_args(A)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
+    P, hold = _make_prec(prec)
+    it, rr = C.c_int(0), C.c_double(0)
+    hist = np.zeros(max(maxit, 1)) if history else None
+    st = lib().or_pcg(A.n, rp, ci, v, C.byref(P), _p(b, _f64p), _p(x, _f64p), int(maxit), float(rtol),
+                      C.byref(it), C.byref(rr), _p(hist, _f64p) if history else None)
+    _check(st, "pcg")
+    out = dict(x=x, iters=it.value, relres=rr.value, status=st)
+    if history:
+        out["hist"] = hist[: it.value]
+    return out
+
+
+def gmres(A: Csr, b, prec=None, x0=None, restart=30, maxit=10000, rtol=1e-8, flexible=False,
+          history=False):
+    """Restarted right-preconditioned (F)GMRES.
+
+    prec: None | ("sait64", M1, M2) | ("sait32", M1, f1, M2, f2) | ("exact", L, U)
+    | ("jacobi", L, U, sweeps) where the preconditioner is z = M2 (M1 r) (for
+    "exact": U^-1 (L^-1 r); "jacobi": s sweeps on L, then on U).
+    Returns dict(x, iters, restarts, relres, est, status[, hist]).
+    """
+    keep, (rp, ci, v) = _csr_args(A)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64)
+    P, hold = _make_prec(prec)
     it, rs = C.c_int(0), C.c_int(0)
     rr, est = C.c_double(0), C.c_double(0)
     hist = np.zeros(max(maxit, 1)) if history else None

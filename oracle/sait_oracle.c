@@ -646,6 +646,7 @@ void or_grad_values(int64_t n, const int32_t *rp, const int32_t *ci,
 #define OR_PREC_SAIT64 1   /* z = M2 (M1 r), FP64 values */
 #define OR_PREC_SAIT32 2   /* z = (double)(M2_32 (M1_32 fl32(r))), binary32 */
 #define OR_PREC_EXACT 3    /* z = U^-1 (L^-1 r): M1 = L (lower), M2 = U (upper) */
+#define OR_PREC_JACOBI 4   /* z = J_U^s (J_L^s r): s Jacobi sweeps on each factor */
 
 typedef struct {
     int kind;
@@ -655,7 +656,47 @@ typedef struct {
     const int32_t *rp2, *ci2;
     const double *v2;
     const float *f2;
+    int sweeps;
 } or_prec;
+
+/*
+ * s Jacobi sweeps for a triangular system T y = r from y = 0 (Sec. 2: the
+ * Jacobi iteration the SAIT series is built from): every sweep computes
+ * y_new_i = (r_i - sum_{j != i} T_ij y_old_j) / T_ii from the previous
+ * iterate.  One sweep gives r / diag(T); with s sweeps the result is the
+ * truncated series of SAIT_Thr(0, s - 1).  Works for lower and upper T.
+ */
+static int jacobi_sweeps(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                         const double *r, int s, double *y) {
+    if (s < 1) return OR_E_INVALID;
+    double *old = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!old) return OR_E_NOMEM;
+    for (int64_t i = 0; i < n; i++) y[i] = 0.0;
+    int st = OR_OK;
+    for (int k = 0; k < s && st == OR_OK; k++) {
+        memcpy(old, y, sizeof(double) * (size_t)n);
+        int bad = 0;
+        /* rows are independent within a sweep: the result does not depend on the threads */
+#pragma omp parallel for schedule(static) reduction(| : bad)
+        for (int64_t i = 0; i < n; i++) {
+            double acc = r[i], d = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+                if (ci[p] == i) d = v[p];
+                else acc = acc - v[p] * old[ci[p]];
+            }
+            if (d == 0.0) bad = 1;
+            else y[i] = acc / d;
+        }
+        if (bad) st = OR_E_ZERO_PIVOT;
+    }
+    free(old);
+    return st;
+}
+
+int or_jacobi_sweeps(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                     const double *r, int s, double *y) {
+    return jacobi_sweeps(n, rp, ci, v, r, s, y);
+}
 
 static int prec_apply(int64_t n, const or_prec *P, const double *r, double *z, double *tmp) {
     switch (P ? P->kind : OR_PREC_NONE) {
@@ -672,6 +713,11 @@ static int prec_apply(int64_t n, const or_prec *P, const double *r, double *z, d
         int st = or_lower_solve(n, P->rp1, P->ci1, P->v1, r, tmp);
         if (st) return st;
         return or_upper_solve(n, P->rp2, P->ci2, P->v2, tmp, z);
+    }
+    case OR_PREC_JACOBI: {
+        int st = jacobi_sweeps(n, P->rp1, P->ci1, P->v1, r, P->sweeps, tmp);
+        if (st) return st;
+        return jacobi_sweeps(n, P->rp2, P->ci2, P->v2, tmp, P->sweeps, z);
     }
     default:
         return OR_E_INVALID;
@@ -795,5 +841,89 @@ int or_gmres(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
     if (relres_out) *relres_out = relres;
     if (est_out) *est_out = est;
     free(V); free(Z); free(H); free(cs); free(sn); free(g); free(y); free(r); free(w); free(z); free(tmp);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Preconditioned conjugate gradients (Sec. 4: the solver of the paper's */
+/* experiments), textbook form (Saad, Alg. 9.1)                         */
+/* ------------------------------------------------------------------ */
+/*
+ * r = b - A x, z = M r, p = z; per iteration: q = A p, alpha = (r, z) / (p, q),
+ * x += alpha p, r -= alpha q, stop once ||r|| / ||b|| <= rtol (the recursively
+ * updated residual), z = M r, beta = (r, z)_new / (r, z)_old, p = z + beta p.
+ * iters = number of x updates; relres = the true ||b - A x|| / ||b|| at the
+ * end; hist (may be NULL, length maxit) receives ||r|| / ||b|| after every
+ * update.  Returns OR_OK, OR_NOT_CONVERGED (maxit) or OR_E_INVALID when
+ * (p, q) = 0 before convergence.
+ */
+int or_pcg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+           const or_prec *P, const double *b, double *x, int maxit, double rtol,
+           int *iters_out, double *relres_out, double *hist) {
+    if (maxit < 0 || !(rtol >= 0.0)) return OR_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(sizeof(double) * nn), *z = (double *)malloc(sizeof(double) * nn);
+    double *p = (double *)malloc(sizeof(double) * nn), *q = (double *)malloc(sizeof(double) * nn);
+    double *tmp = (double *)malloc(sizeof(double) * nn);
+    int st = OR_OK, it = 0;
+    if (!r || !z || !p || !q || !tmp) {
+        st = OR_E_NOMEM;
+        goto done;
+    }
+    or_spmv(n, rp, ci, v, x, q);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+    double nb = sqrt(dot(n, b, b));
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+        goto done;
+    }
+    if (sqrt(dot(n, r, r)) / nb <= rtol) goto done;
+    st = prec_apply(n, P, r, z, tmp);
+    if (st) goto done;
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    double rz = dot(n, r, z);
+    st = OR_NOT_CONVERGED;
+    while (it < maxit) {
+        or_spmv(n, rp, ci, v, p, q);
+        double pq = dot(n, p, q);
+        if (pq == 0.0) {
+            st = OR_E_INVALID;
+            break;
+        }
+        double alpha = rz / pq;
+        for (int64_t i = 0; i < n; i++) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * q[i];
+        }
+        it++;
+        double rel = sqrt(dot(n, r, r)) / nb;
+        if (hist) hist[it - 1] = rel;
+        if (rel <= rtol) {
+            st = OR_OK;
+            break;
+        }
+        int s2 = prec_apply(n, P, r, z, tmp);
+        if (s2) {
+            st = s2;
+            break;
+        }
+        double rz_new = dot(n, r, z);
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+    }
+done:
+    if (st >= 0 && relres_out) {
+        or_spmv(n, rp, ci, v, x, q);
+        double nb2 = sqrt(dot(n, b, b)), rr = 0.0;
+        for (int64_t i = 0; i < n; i++) rr += (b[i] - q[i]) * (b[i] - q[i]);
+        *relres_out = nb2 > 0.0 ? sqrt(rr) / nb2 : 0.0;
+    }
+    if (iters_out) *iters_out = it;
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(tmp);
     return st;
 }
