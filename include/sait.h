@@ -89,9 +89,29 @@ typedef struct {
 typedef struct {
     int restart;         /* GMRES restart length k >= 1 [30] */
     int maxit;           /* maximum total inner iterations [10000] */
-    double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual) [1e-8] */
+    double rtol;         /* stop when ||b - A x||_2 <= rtol ||b||_2 (true residual for GMRES,
+                            the recursively updated residual for PCG) [1e-8] */
     int flexible;        /* 0: right-preconditioned GMRES; 1: FGMRES (stores M v_j) [0] */
+    int method;          /* SAIT_METHOD_GMRES [default] or SAIT_METHOD_PCG */
 } sait_solve_opts;
+
+/* Krylov methods of sait_solve.  PCG (Sec. 4 of the paper: the solver of
+ * its experiments) is the textbook preconditioned conjugate gradient method
+ * for symmetric positive definite A; the SAIT preconditioner M_U M_L is not
+ * symmetric (its factors are built by the same left-multiplied recursion),
+ * as in the paper's runs.  PCG is single system, one right-hand side, not
+ * transposed. */
+enum { SAIT_METHOD_GMRES = 0, SAIT_METHOD_PCG = 1 };
+
+/* Preconditioners sait_apply / sait_solve use (sait_set_preconditioner):
+ * SAIT: z = M_U (M_L r) [default];
+ * JACOBI: s Jacobi sweeps from zero on L, then on U -- the paper's
+ *   comparison (Sec. 4), equal to the SAIT series with no dropping and
+ *   m = s - 1 (Sec. 2) evaluated without forming it;
+ * EXACT: the forward and backward substitutions with L and U
+ *   (level-scheduled);
+ * NONE: z = r. */
+enum { SAIT_PREC_SAIT = 0, SAIT_PREC_JACOBI = 1, SAIT_PREC_EXACT = 2, SAIT_PREC_NONE = 3 };
 
 /* Per-(system, right-hand side) solve report. */
 typedef struct {
@@ -191,6 +211,18 @@ int sait_query(sait_handle h, int64_t *n, int64_t *nnz_A, int64_t *nnz_L, int64_
  */
 int sait_export(sait_handle h, int which, int32_t *row_ptr, int32_t *col_idx, double *val,
                 void *stored);
+
+/*
+ * Select the preconditioner of later sait_apply / sait_solve calls on this
+ * handle (kind = SAIT_PREC_*; sweeps >= 1 for SAIT_PREC_JACOBI, ignored
+ * otherwise).  Builds what the kind needs from the ILU factors on first use
+ * (the off-diagonal parts and diagonals for Jacobi, the dependency levels
+ * for the exact solves).  Kinds other than SAIT apply to single-system,
+ * single right-hand side, non-transposed calls; the others fail with
+ * SAIT_E_INVALID while one is selected.  Errors: SAIT_E_INVALID (bad kind,
+ * sweeps < 1), SAIT_E_ZERO_PIVOT (zero diagonal in L or U).
+ */
+int sait_set_preconditioner(sait_handle h, int kind, int sweeps, void *hip_stream);
 
 /* Release the handle and all device memory it owns (NULL is a no-op). */
 void sait_destroy(sait_handle h);

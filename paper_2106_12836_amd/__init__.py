@@ -28,6 +28,7 @@ from .sait import (  # noqa: F401
     sait_matvec,
     sait_query,
     sait_set_apply_lanes,
+    sait_set_preconditioner,
     sait_set_values,
     sait_solve,
     sait_time_apply,

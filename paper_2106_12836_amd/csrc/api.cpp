@@ -74,9 +74,15 @@ struct sait_handle_s {
     bool has_transpose = false;
     int lanesA = 8, lanesL = 8, lanesU = 8, lanesAt = 8, lanesLt = 8, lanesUt = 8;
     DevBuf tmp;     // apply intermediate
+    DevBuf tmp2;    // second apply scratch (Jacobi sweeps)
     DevBuf At_perm; // At.v[q] = A.v[At_perm[q]]
     Solver solver;
     BatchedSolver batched;
+    // preconditioner selected by sait_set_preconditioner (built on first use)
+    int prec_kind = SAIT_PREC_SAIT;
+    int sweeps = 1;
+    std::unique_ptr<JacobiFactor> JL, JU;
+    std::unique_ptr<LevelFactor> EL, EU;
 };
 
 namespace {
@@ -113,7 +119,48 @@ void ensure_tmp(sait_handle h, int64_t elems, size_t esize) {
     if (h->tmp.bytes() < need) h->tmp.alloc(&h->alloc, need);
 }
 
+// Preconditioner operands of a single-system, non-transposed solve or apply.
+Ops solve_ops(sait_handle h, int transpose) {
+    Ops ops;
+    ops.A = transpose ? &h->At : &h->A;
+    ops.M1 = transpose ? &h->MUt : &h->ML;
+    ops.M2 = transpose ? &h->MLt : &h->MU;
+    ops.lanesA = transpose ? h->lanesAt : h->lanesA;
+    ops.lanes1 = transpose ? h->lanesUt : h->lanesL;
+    ops.lanes2 = transpose ? h->lanesLt : h->lanesU;
+    ops.precision = h->opts.precision;
+    ops.prec_kind = h->prec_kind;
+    ops.sweeps = h->sweeps;
+    ops.JL = h->JL.get();
+    ops.JU = h->JU.get();
+    ops.EL = h->EL.get();
+    ops.EU = h->EU.get();
+    return ops;
+}
+
 void apply_impl(sait_handle h, const double *r, double *z, int nrhs, int64_t ld, int transpose, hipStream_t s) {
+    if (h->prec_kind != SAIT_PREC_SAIT) {
+        if (nrhs != 1 || ld != 1 || transpose)
+            fail(SAIT_E_INVALID, "the Jacobi / exact / no preconditioner applies to one non-transposed vector");
+        const int64_t n = h->n;
+        ensure_tmp(h, n, sizeof(double));
+        if (h->tmp2.bytes() < (size_t)std::max<int64_t>(n, 1) * sizeof(double))
+            h->tmp2.alloc(&h->alloc, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+        double *t1 = h->tmp.as<double>(), *t2 = h->tmp2.as<double>();
+        switch (h->prec_kind) {
+        case SAIT_PREC_JACOBI:
+            jacobi_apply(*h->JL, h->sweeps, r, t1, t2, s);
+            jacobi_apply(*h->JU, h->sweeps, t1, z, t2, s);
+            break;
+        case SAIT_PREC_EXACT:
+            level_solve(*h->EL, r, t1, s);
+            level_solve(*h->EU, t1, z, s);
+            break;
+        default:
+            if (n) SAIT_HIP(hipMemcpyAsync(z, r, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        return;
+    }
     const DevCsr *M1 = transpose ? &h->MUt : &h->ML;
     const DevCsr *M2 = transpose ? &h->MLt : &h->MU;
     const int l1 = transpose ? h->lanesUt : h->lanesL;
@@ -161,6 +208,7 @@ void sait_default_solve_opts(sait_solve_opts *o) {
     o->maxit = 10000;
     o->rtol = 1e-8;
     o->flexible = 0;
+    o->method = SAIT_METHOD_GMRES;
 }
 
 const char *sait_last_error(void) { return g_last_error.c_str(); }
@@ -299,6 +347,14 @@ int sait_solve(sait_handle h, const double *b, double *x, int nrhs, int64_t ld, 
         sait_solve_opts opts;
         sait_default_solve_opts(&opts);
         if (o) opts = *o;
+        if (opts.method != SAIT_METHOD_GMRES && opts.method != SAIT_METHOD_PCG) fail(SAIT_E_INVALID, "unknown method");
+        if (opts.method == SAIT_METHOD_PCG) {
+            if (h->nsys != 1 || nrhs != 1 || ld != 1 || transpose)
+                fail(SAIT_E_INVALID, "PCG solves one system with one non-transposed right-hand side");
+            return h->solver.pcg(&h->alloc, solve_ops(h, 0), b, x, opts, info, as_stream(hip_stream));
+        }
+        if (h->prec_kind != SAIT_PREC_SAIT && (h->nsys != 1 || nrhs != 1 || ld != 1 || transpose))
+            fail(SAIT_E_INVALID, "the Jacobi / exact / no preconditioner serves single, non-transposed solves");
         if (h->nsys != 1 || nrhs != 1 || ld != 1) {
             if (transpose) fail(SAIT_E_INVALID, "batched solves are not transposed");
             BatchedOps bo;
@@ -321,15 +377,45 @@ int sait_solve(sait_handle h, const double *b, double *x, int nrhs, int64_t ld, 
             }
             return status;
         }
-        Ops ops;
-        ops.A = transpose ? &h->At : &h->A;
-        ops.M1 = transpose ? &h->MUt : &h->ML;
-        ops.M2 = transpose ? &h->MLt : &h->MU;
-        ops.lanesA = transpose ? h->lanesAt : h->lanesA;
-        ops.lanes1 = transpose ? h->lanesUt : h->lanesL;
-        ops.lanes2 = transpose ? h->lanesLt : h->lanesU;
-        ops.precision = h->opts.precision;
-        return h->solver.solve(&h->alloc, ops, b, x, opts, info, as_stream(hip_stream));
+        return h->solver.solve(&h->alloc, solve_ops(h, transpose), b, x, opts, info, as_stream(hip_stream));
+    });
+}
+
+int sait_set_preconditioner(sait_handle h, int kind, int sweeps, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        hipStream_t s = as_stream(hip_stream);
+        switch (kind) {
+        case SAIT_PREC_SAIT:
+        case SAIT_PREC_NONE:
+            break;
+        case SAIT_PREC_JACOBI:
+            if (sweeps < 1) fail(SAIT_E_INVALID, "Jacobi sweeps must be >= 1");
+            if (!h->JL) {
+                auto JL = std::make_unique<JacobiFactor>();
+                auto JU = std::make_unique<JacobiFactor>();
+                build_jacobi(&h->alloc, h->L_h, *JL, s);
+                build_jacobi(&h->alloc, h->U_h, *JU, s);
+                h->JL = std::move(JL);
+                h->JU = std::move(JU);
+            }
+            h->sweeps = sweeps;
+            break;
+        case SAIT_PREC_EXACT:
+            if (!h->EL) {
+                auto EL = std::make_unique<LevelFactor>();
+                auto EU = std::make_unique<LevelFactor>();
+                build_levels(&h->alloc, h->L_h, true, *EL, s);
+                build_levels(&h->alloc, h->U_h, false, *EU, s);
+                h->EL = std::move(EL);
+                h->EU = std::move(EU);
+            }
+            break;
+        default:
+            fail(SAIT_E_INVALID, "unknown preconditioner kind");
+        }
+        h->prec_kind = kind;
+        return SAIT_OK;
     });
 }
 

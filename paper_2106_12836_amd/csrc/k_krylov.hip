@@ -523,6 +523,156 @@ __global__ void k_init_state(GmresDev *st, int restart, int maxit, double rtol) 
     st->nb = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Preconditioned conjugate gradients (textbook form; the solver of the
+// paper's experiments, Sec. 4):
+//   r = b - A x, z = M r, p = z; per iteration q = A p,
+//   alpha = (r, z) / (p, q), x += alpha p, r -= alpha q, stop once
+//   ||r|| / ||b|| <= rtol, z = M r, beta = (r, z)_new / (r, z)_old,
+//   p = z + beta p.
+// Each kernel reads `done` first; the reductions are per-block partials
+// summed by the last block in block order.
+// ---------------------------------------------------------------------------
+
+// Partial sums of x.y (and u.w if u) of the block's rows into part[0 / 1][blk];
+// returns true in the last block, whose thread 0 then holds the totals.
+__device__ bool pcg_dots(int64_t n, const double *x, const double *y, const double *u, const double *w, double *part,
+                         unsigned *counter, double &t0, double &t1) {
+    __shared__ double sh[4];
+    const int B = gridDim.x;
+    const Rows R = block_rows(n, B);
+    double a = 0.0, c = 0.0;
+    for (int64_t r = R.lo + threadIdx.x; r < R.hi; r += kNT) {
+        a = fma(x[r], y[r], a);
+        if (u) c = fma(u[r], w[r], c);
+    }
+    a = block_sum(a, sh);
+    if (u) c = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        if (u) part[B + blockIdx.x] = c;
+    }
+    if (!last_block(counter)) return false;
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < B; b += kNT) {
+        s0 += part[b];
+        if (u) s1 += part[B + b];
+    }
+    t0 = block_sum(s0, sh);
+    t1 = u ? block_sum(s1, sh) : 0.0;
+    if (threadIdx.x == 0) *counter = 0;
+    return true;
+}
+
+// ||b||, ||r0||: start of the iteration (done when b = 0 or already converged)
+__global__ __launch_bounds__(kNT) void k_pcg_start(int64_t n, const double *__restrict__ b, const double *__restrict__ r,
+                                                   PcgDev *st, double *part, unsigned *counter, Mailbox *mb) {
+    double bb, rr;
+    if (!pcg_dots(n, b, b, r, r, part, counter, bb, rr)) return;
+    if (threadIdx.x != 0) return;
+    st->nb = sqrt(bb);
+    st->relres = st->nb > 0.0 ? sqrt(rr) / st->nb : 0.0;
+    st->iters = 0;
+    st->breakdown = 0;
+    st->done = (st->nb == 0.0 || st->relres <= st->rtol || st->maxit == 0) ? 1 : 0;
+    if (mb) {
+        mb->iters = 0;
+        __threadfence_system();
+        __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// (r, z): rz on the first call, beta = rz_new / rz afterwards
+__global__ __launch_bounds__(kNT) void k_pcg_rz(int64_t n, const double *__restrict__ r, const double *__restrict__ z,
+                                                PcgDev *st, int first, double *part, unsigned *counter) {
+    if (st->done) return;
+    double rz, unused;
+    if (!pcg_dots(n, r, z, nullptr, nullptr, part, counter, rz, unused)) return;
+    if (threadIdx.x != 0) return;
+    if (!first) st->beta = rz / st->rz;
+    st->rz = rz;
+}
+
+// p = z (first) or p = z + beta p
+__global__ void k_pcg_dir(int64_t n, const double *__restrict__ z, double *__restrict__ p, const PcgDev *st,
+                          int first) {
+    if (st->done) return;
+    const double beta = first ? 0.0 : st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = first ? z[i] : fma(beta, p[i], z[i]);
+}
+
+// alpha = (r, z) / (p, q); (p, q) = 0 ends the iteration (breakdown)
+__global__ __launch_bounds__(kNT) void k_pcg_alpha(int64_t n, const double *__restrict__ p,
+                                                   const double *__restrict__ q, PcgDev *st, double *part,
+                                                   unsigned *counter, Mailbox *mb) {
+    if (st->done) return;
+    double pq, unused;
+    if (!pcg_dots(n, p, q, nullptr, nullptr, part, counter, pq, unused)) return;
+    if (threadIdx.x != 0) return;
+    if (pq == 0.0) {
+        st->breakdown = 1;
+        st->done = 1;
+        if (mb) {
+            __threadfence_system();
+            __hip_atomic_store(&mb->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        return;
+    }
+    st->alpha = st->rz / pq;
+}
+
+// x += alpha p, r -= alpha q, ||r||: count the iteration, decide convergence
+__global__ __launch_bounds__(kNT) void k_pcg_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ q,
+                                                double *__restrict__ x, double *__restrict__ r, PcgDev *st,
+                                                double *part, unsigned *counter, Mailbox *mb) {
+    __shared__ double sh[4];
+    if (st->done) return;
+    const double alpha = st->alpha;
+    const int B = gridDim.x;
+    const Rows R = block_rows(n, B);
+    double a = 0.0;
+    for (int64_t i = R.lo + threadIdx.x; i < R.hi; i += kNT) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        a = fma(ri, ri, a);
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+    if (!last_block(counter)) return;
+    double s0 = 0.0;
+    for (int b = threadIdx.x; b < B; b += kNT) s0 += part[b];
+    const double rr = block_sum(s0, sh);
+    if (threadIdx.x != 0) return;
+    *counter = 0;
+    st->iters += 1;
+    st->relres = sqrt(rr) / st->nb;
+    st->done = (st->relres <= st->rtol || st->iters >= st->maxit) ? 1 : 0;
+    if (mb) {
+        mb->iters = st->iters;
+        mb->est = st->relres;
+        __threadfence_system();
+        __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// ||res||^2 into true_rr (res = b - A x at the end)
+__global__ __launch_bounds__(kNT) void k_pcg_true(int64_t n, const double *__restrict__ res, PcgDev *st, double *part,
+                                                  unsigned *counter) {
+    double rr, unused;
+    if (!pcg_dots(n, res, res, nullptr, nullptr, part, counter, rr, unused)) return;
+    if (threadIdx.x == 0) st->true_rr = rr;
+}
+
+__global__ void k_pcg_init(PcgDev *st, int maxit, double rtol) {
+    st->maxit = maxit;
+    st->rtol = rtol;
+    st->done = 0;
+    st->iters = 0;
+    st->breakdown = 0;
+}
+
 // Grid of the inner-product passes: up to 512 blocks of >= 2048 rows.
 int reduce_blocks(int64_t n) {
     const int64_t b = (n + 2047) / 2048;
@@ -601,14 +751,121 @@ void Solver::ensure(Allocator *a, int64_t n, int restart, bool flexible, int pre
     SAIT_HIP(hipMemcpy(st_.as<void>(), &h, sizeof(h), hipMemcpyHostToDevice));
 }
 
+void Solver::ensure_prec_tmp(Allocator *a, int64_t n, int precision) {
+    const size_t nn = (size_t)std::max<int64_t>(n, 64);
+    if (zt_.bytes() < nn * sizeof(double)) zt_.alloc(a, nn * sizeof(double));
+    if (pt1_.bytes() < nn * sizeof(double)) pt1_.alloc(a, nn * sizeof(double));
+    if (precision != SAIT_F64 && y32_.bytes() < nn * sizeof(float)) y32_.alloc(a, nn * sizeof(float));
+}
+
 void Solver::apply_prec(const Ops &ops, const double *in, double *out, hipStream_t s) {
-    if (ops.precision == SAIT_F64) {
-        spmv(*ops.M1, in, XKind::F64, zt_.as<double>(), YKind::F64, 1, 1, 1, ops.lanes1, s);
-        spmv(*ops.M2, zt_.as<double>(), XKind::F64, out, YKind::F64, 1, 1, 1, ops.lanes2, s);
-    } else {
-        spmv(*ops.M1, in, XKind::F64, y32_.as<float>(), YKind::F32, 1, 1, 1, ops.lanes1, s);
-        spmv(*ops.M2, y32_.as<float>(), XKind::F32, out, YKind::F64, 1, 1, 1, ops.lanes2, s);
+    const int64_t n = ops.A->n;
+    switch (ops.prec_kind) {
+    case SAIT_PREC_SAIT:
+        if (ops.precision == SAIT_F64) {
+            spmv(*ops.M1, in, XKind::F64, zt_.as<double>(), YKind::F64, 1, 1, 1, ops.lanes1, s);
+            spmv(*ops.M2, zt_.as<double>(), XKind::F64, out, YKind::F64, 1, 1, 1, ops.lanes2, s);
+        } else {
+            spmv(*ops.M1, in, XKind::F64, y32_.as<float>(), YKind::F32, 1, 1, 1, ops.lanes1, s);
+            spmv(*ops.M2, y32_.as<float>(), XKind::F32, out, YKind::F64, 1, 1, 1, ops.lanes2, s);
+        }
+        return;
+    case SAIT_PREC_JACOBI:
+        jacobi_apply(*ops.JL, ops.sweeps, in, zt_.as<double>(), pt1_.as<double>(), s);
+        jacobi_apply(*ops.JU, ops.sweeps, zt_.as<double>(), out, pt1_.as<double>(), s);
+        return;
+    case SAIT_PREC_EXACT:
+        level_solve(*ops.EL, in, zt_.as<double>(), s);
+        level_solve(*ops.EU, zt_.as<double>(), out, s);
+        return;
+    case SAIT_PREC_NONE:
+        if (n) SAIT_HIP(hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return;
+    default:
+        fail(SAIT_E_INVALID, "unknown preconditioner kind");
     }
+}
+
+int Solver::pcg(Allocator *a, const Ops &ops, const double *b, double *x, const sait_solve_opts &o,
+                sait_solve_info *info, hipStream_t s) {
+    const int64_t n = ops.A->n;
+    if (o.maxit < 0) fail(SAIT_E_INVALID, "maxit must be >= 0");
+    if (!(o.rtol >= 0.0)) fail(SAIT_E_INVALID, "rtol must be >= 0");
+    ensure_prec_tmp(a, n, ops.precision);
+    if (pn_ != n) {
+        const size_t nn = (size_t)std::max<int64_t>(n, 64) * sizeof(double);
+        pr_.alloc(a, nn);
+        pz_.alloc(a, nn);
+        pp_.alloc(a, nn);
+        pq_.alloc(a, nn);
+        pst_.alloc(a, sizeof(PcgDev));
+        ppart_.alloc(a, sizeof(double) * 2 * 1024);
+        if (counters_.empty()) {
+            counters_.alloc(a, 4 * sizeof(unsigned));
+            SAIT_HIP(hipMemset(counters_.as<void>(), 0, 4 * sizeof(unsigned)));
+        }
+        if (!mailbox_) SAIT_HIP(hipHostMalloc(&mailbox_, 256, hipHostMallocMapped));
+        pn_ = n;
+    }
+    PcgDev *st = pst_.as<PcgDev>();
+    Mailbox *mbh = reinterpret_cast<Mailbox *>(mailbox_);
+    Mailbox *mbd = nullptr;
+    SAIT_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&mbd), mailbox_, 0));
+    double *r = pr_.as<double>(), *z = pz_.as<double>(), *p = pp_.as<double>(), *q = pq_.as<double>();
+    double *part = ppart_.as<double>();
+    unsigned *cnt = counters_.as<unsigned>();
+    const int RB = std::min(reduce_blocks(n), 1024);
+    const int SB = stream_blocks(n);
+
+    hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1), 0, s, st, o.maxit, o.rtol);
+    spmv(*ops.A, x, XKind::F64, r, YKind::F64, 1, 1, 1, ops.lanesA, s, b);  // r = b - A x
+    hipLaunchKernelGGL(k_pcg_start, dim3(RB), dim3(kNT), 0, s, n, b, r, st, part, cnt, mbd);
+    SAIT_LAUNCH_CHECK();
+    PcgDev hs{};
+    SAIT_HIP(hipMemcpyAsync(&hs, st, sizeof(PcgDev), hipMemcpyDeviceToHost, s));
+    SAIT_HIP(hipStreamSynchronize(s));
+    if (hs.nb == 0.0) {
+        if (n) SAIT_HIP(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+        SAIT_HIP(hipStreamSynchronize(s));
+        fill_info(info, 0, 0, SAIT_OK, 0.0, 0.0);
+        return SAIT_OK;
+    }
+    if (!hs.done) {
+        apply_prec(ops, r, z, s);
+        hipLaunchKernelGGL(k_pcg_rz, dim3(RB), dim3(kNT), 0, s, n, r, z, st, 1, part, cnt);
+        hipLaunchKernelGGL(k_pcg_dir, dim3(SB), dim3(256), 0, s, n, z, p, st, 1);
+        SAIT_LAUNCH_CHECK();
+        // iterations, a few queued ahead of the polled mailbox
+        constexpr int kAhead = 3;
+        hipEvent_t ev[kAhead + 1];
+        for (auto &e : ev) SAIT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        bool stop = false;
+        for (int it = 0; it < o.maxit && !stop; ++it) {
+            spmv(*ops.A, p, XKind::F64, q, YKind::F64, 1, 1, 1, ops.lanesA, s);
+            hipLaunchKernelGGL(k_pcg_alpha, dim3(RB), dim3(kNT), 0, s, n, p, q, st, part, cnt, mbd);
+            hipLaunchKernelGGL(k_pcg_xr, dim3(RB), dim3(kNT), 0, s, n, p, q, x, r, st, part, cnt, mbd);
+            apply_prec(ops, r, z, s);
+            hipLaunchKernelGGL(k_pcg_rz, dim3(RB), dim3(kNT), 0, s, n, r, z, st, 0, part, cnt);
+            hipLaunchKernelGGL(k_pcg_dir, dim3(SB), dim3(256), 0, s, n, z, p, st, 0);
+            SAIT_LAUNCH_CHECK();
+            SAIT_HIP(hipEventRecord(ev[it % (kAhead + 1)], s));
+            if (it >= kAhead) {
+                SAIT_HIP(hipEventSynchronize(ev[(it - kAhead) % (kAhead + 1)]));
+                if (__hip_atomic_load(&mbh->done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) stop = true;
+            }
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+    // true residual
+    spmv(*ops.A, x, XKind::F64, q, YKind::F64, 1, 1, 1, ops.lanesA, s, b);
+    hipLaunchKernelGGL(k_pcg_true, dim3(RB), dim3(kNT), 0, s, n, q, st, part, cnt);
+    SAIT_LAUNCH_CHECK();
+    SAIT_HIP(hipMemcpyAsync(&hs, st, sizeof(PcgDev), hipMemcpyDeviceToHost, s));
+    SAIT_HIP(hipStreamSynchronize(s));
+    const double true_rel = sqrt(hs.true_rr) / hs.nb;
+    const int status = (hs.relres <= o.rtol && !hs.breakdown) ? SAIT_OK : SAIT_NOT_CONVERGED;
+    fill_info(info, hs.iters, 0, status, hs.relres, true_rel);
+    return status;
 }
 
 int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, const sait_solve_opts &o,
@@ -619,6 +876,7 @@ int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, cons
     if (o.maxit < 0) fail(SAIT_E_INVALID, "maxit must be >= 0");
     if (!(o.rtol >= 0.0)) fail(SAIT_E_INVALID, "rtol must be >= 0");
     ensure(a, n, k, o.flexible != 0, ops.precision);
+    ensure_prec_tmp(a, n, ops.precision);
     GmresDev *st = st_.as<GmresDev>();
     Mailbox *mbh = reinterpret_cast<Mailbox *>(mailbox_);
     Mailbox *mbd = nullptr;

@@ -500,6 +500,51 @@ void dispatch(const DevCsr &M, const void *x, void *y, int nrhs, int64_t ldx, in
     else dispatch_block<4, VT, XT, AT, YT>(M, x, ldx, y, ldy, nrhs, shape, s);
 }
 
+// One Jacobi sweep for a triangular system T y = r on the sliced-ELL copy of
+// N, the off-diagonal part of T, and its diagonal d:
+//   ynew_i = (r_i - sum_j N_ij yold_j) / d_i,
+// the products subtracted from r_i one by one in column order with separate
+// roundings (one row per lane, two groups of 4 entries per stage).
+__global__ __launch_bounds__(kBlock) void k_jacobi_sell(int n, int nslices, const int64_t *__restrict__ sptr,
+                                                        const int *__restrict__ rp, const int *__restrict__ sci,
+                                                        const double *__restrict__ sv, const double *__restrict__ d,
+                                                        const double *__restrict__ r, const double *__restrict__ yold,
+                                                        double *__restrict__ ynew) {
+    const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+    const int s = (int)blk * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63;
+    if (s >= nslices) return;
+    const int row = s * 64 + l;
+    const int len = row < n ? rp[row + 1] - rp[row] : 0;
+    const int64_t base = sptr[s];
+    const int ngroups = (int)((sptr[s + 1] - base) >> 8);
+    double acc = row < n ? r[row] : 0.0;
+    int cols[2][4];
+    double vals[2][4];
+    if (ngroups > 0) {
+        load_idx4(sci + base + 4 * l, cols[0]);
+        load_quad(sv + base, l, vals[0]);
+    }
+    for (int g = 0; g < ngroups; ++g) {
+        const int cur = g & 1;
+        if (g + 1 < ngroups) {
+            const int64_t grp = base + (int64_t)(g + 1) * 256;
+            load_idx4(sci + grp + 4 * l, cols[cur ^ 1]);
+            load_quad(sv + grp, l, vals[cur ^ 1]);
+        }
+        double xs[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xs[j] = (g * 4 + j < len) ? yold[cols[cur][j]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (g * 4 + j < len) {
+#pragma clang fp contract(off)
+                acc = acc - mul_rn(vals[cur][j], xs[j]);
+            }
+    }
+    if (row < n) ynew[row] = acc / d[row];
+}
+
 }  // namespace
 
 bool valid_shape(int shape) {
@@ -626,6 +671,17 @@ void spmv(const DevCsr &M, const void *x, XKind xk, void *y, YKind yk, int nrhs,
             return dispatch<Bf16, double, float, double>(M, x, y, nrhs, ldx, ldy, lanes, s, nullptr);
     }
     fail(SAIT_E_INVALID, "unsupported precision / vector type combination");
+}
+
+
+void jacobi_sweep(const DevCsr &N, const double *d, const double *r, const double *yold, double *ynew, hipStream_t s) {
+    if (N.n == 0) return;
+    if (N.precision != SAIT_F64 || N.nslices <= 0) fail(SAIT_E_INVALID, "jacobi_sweep needs an FP64 sliced-ELL matrix");
+    const int grid = (int)((N.nslices + kBlock / 64 - 1) / (kBlock / 64));
+    hipLaunchKernelGGL(k_jacobi_sell, dim3(grid), dim3(kBlock), 0, s, (int)N.n, (int)N.nslices,
+                       N.sell_ptr.as<int64_t>(), N.rp.as<int>(), N.sell_ci.as<int>(), N.sell_v.as<double>(), d, r,
+                       yold, ynew);
+    SAIT_LAUNCH_CHECK();
 }
 
 }  // namespace sait

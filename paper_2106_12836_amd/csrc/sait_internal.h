@@ -167,6 +167,31 @@ void prepare_sell(Allocator *a, DevCsr &M, hipStream_t s);
 // Row blocks for the LDS-staged kernel (host pass over the row pointers).
 void prepare_stream(Allocator *a, DevCsr &M, hipStream_t s);
 
+// One Jacobi sweep ynew = (r - N yold) / d on the FP64 sliced-ELL matrix N.
+void jacobi_sweep(const DevCsr &N, const double *d, const double *r, const double *yold, double *ynew, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Comparison preconditioners (k_precond.hip)
+// ---------------------------------------------------------------------------
+// Jacobi sweeps on a triangular factor T: N = T without its diagonal
+// (sliced ELL), d = diag(T).
+struct JacobiFactor {
+    DevCsr N;
+    DevBuf d;
+};
+void build_jacobi(Allocator *a, const HostCsr &T, JacobiFactor &J, hipStream_t s);
+// y = s Jacobi sweeps from zero for T y = r (tmp: n doubles of scratch).
+void jacobi_apply(const JacobiFactor &J, int sweeps, const double *r, double *y, double *tmp, hipStream_t s);
+// Level-scheduled exact solve with a triangular factor (rows grouped by
+// dependency level; level_ptr on the host).
+struct LevelFactor {
+    DevCsr T;
+    DevBuf rows;
+    std::vector<int> level_ptr;
+};
+void build_levels(Allocator *a, const HostCsr &T, bool lower, LevelFactor &F, hipStream_t s);
+void level_solve(const LevelFactor &F, const double *b, double *x, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Krylov building blocks (k_krylov.hip)
 // ---------------------------------------------------------------------------

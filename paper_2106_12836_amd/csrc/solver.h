@@ -15,11 +15,23 @@ struct GmresDev {
     int restart, maxit, iters, jc, done;
 };
 
-// Operators of one solve: A (FP64) and the preconditioner z = M2 (M1 v).
+// Operators of one solve: A (FP64) and the preconditioner: SAIT z = M2 (M1 v)
+// (default), s Jacobi sweeps on L then U, the exact solves with L then U,
+// or none.
 struct Ops {
     const DevCsr *A = nullptr, *M1 = nullptr, *M2 = nullptr;
     int lanesA = 8, lanes1 = 8, lanes2 = 8;
     int precision = SAIT_F64;
+    int prec_kind = SAIT_PREC_SAIT;
+    int sweeps = 1;
+    const JacobiFactor *JL = nullptr, *JU = nullptr;
+    const LevelFactor *EL = nullptr, *EU = nullptr;
+};
+
+// Device state of a PCG solve.
+struct PcgDev {
+    double nb, rz, alpha, beta, relres, rtol, true_rr;
+    int iters, maxit, done, breakdown;
 };
 
 class Solver {
@@ -30,16 +42,24 @@ class Solver {
     ~Solver();
     int solve(Allocator *a, const Ops &ops, const double *b, double *x, const sait_solve_opts &o,
               sait_solve_info *info, hipStream_t s);
+    // Preconditioned conjugate gradients (o.method == SAIT_METHOD_PCG).
+    int pcg(Allocator *a, const Ops &ops, const double *b, double *x, const sait_solve_opts &o,
+            sait_solve_info *info, hipStream_t s);
+    // z = M r with the preconditioner of ops (r and z distinct, n doubles).
+    void apply_prec(const Ops &ops, const double *in, double *out, hipStream_t s);
 
   private:
     void ensure(Allocator *a, int64_t n, int restart, bool flexible, int precision);
-    void apply_prec(const Ops &ops, const double *in, double *out, hipStream_t s);
+    void ensure_prec_tmp(Allocator *a, int64_t n, int precision);
     static void fill_info(sait_solve_info *info, int iters, int restarts, int status, double est, double relres);
 
     int64_t n_ = -1, ldv_ = 0;
     int restart_ = 0;
     bool flex_ = false;
     DevBuf V_, Z_, zt_, ut_, y32_, arr_, st_, part_, counters_;
+    DevBuf pt1_, pt2_;                      // preconditioner scratch (Jacobi sweeps, exact solves)
+    DevBuf pr_, pz_, pp_, pq_, pst_, ppart_;  // PCG vectors, state, partial sums
+    int64_t pn_ = -1;
     void *mailbox_ = nullptr;
 };
 

@@ -22,6 +22,9 @@ _LIB = None
 SAIT_OK, SAIT_NOT_CONVERGED = 0, 1
 SAIT_E_INVALID, SAIT_E_ZERO_PIVOT, SAIT_E_NONFINITE, SAIT_E_NOMEM, SAIT_E_DEVICE = -1, -2, -3, -4, -5
 SAIT_ILU0, SAIT_ILUT = 0, 1
+SAIT_METHOD_GMRES, SAIT_METHOD_PCG = 0, 1
+SAIT_PREC_SAIT, SAIT_PREC_JACOBI, SAIT_PREC_EXACT, SAIT_PREC_NONE = 0, 1, 2, 3
+PREC_KINDS = {"sait": SAIT_PREC_SAIT, "jacobi": SAIT_PREC_JACOBI, "exact": SAIT_PREC_EXACT, "none": SAIT_PREC_NONE}
 SAIT_F64, SAIT_F32, SAIT_BF16 = 0, 1, 2
 SAIT_MAT_A, SAIT_MAT_L, SAIT_MAT_U, SAIT_MAT_ML, SAIT_MAT_MU = 0, 1, 2, 3, 4
 PRECISIONS = {"f64": SAIT_F64, "f32": SAIT_F32, "bf16": SAIT_BF16}
@@ -30,6 +33,7 @@ EXPORTED = (
     "sait_default_build_opts", "sait_default_solve_opts", "sait_build", "sait_apply", "sait_matvec",
     "sait_solve", "sait_set_values", "sait_grad_values", "sait_query", "sait_export", "sait_destroy", "sait_last_error",
     "sait_autotune", "sait_set_apply_lanes", "sait_get_apply_lanes", "sait_time_apply", "sait_debug_step", "sait_copy",
+    "sait_set_preconditioner",
 )
 
 
@@ -52,7 +56,8 @@ class sait_build_opts(C.Structure):
 
 
 class sait_solve_opts(C.Structure):
-    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double), ("flexible", C.c_int)]
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double), ("flexible", C.c_int),
+                ("method", C.c_int)]
 
 
 class sait_solve_info(C.Structure):
@@ -95,6 +100,7 @@ def lib():
         L.sait_get_apply_lanes.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sait_time_apply.argtypes = [vp, vp, vp, C.c_int, vp, f64p, f64p, f64p]
         L.sait_copy.argtypes = [vp, vp, C.c_size_t, vp]
+        L.sait_set_preconditioner.argtypes = [vp, C.c_int, C.c_int, vp]
         L.sait_debug_step.argtypes = [i64, i32p, i32p, f64p, i32p, i32p, f64p, C.c_double, C.c_int, i64,
                                       i32p, i32p, f64p, C.POINTER(C.c_int64)]
         _LIB = L
@@ -238,6 +244,12 @@ def sait_destroy(h):
         lib().sait_destroy(h)
 
 
+def sait_set_preconditioner(h, kind, sweeps=1, stream=None):
+    if isinstance(kind, str):
+        kind = PREC_KINDS[kind]
+    return _check(lib().sait_set_preconditioner(h, int(kind), int(sweeps), _stream(stream)))
+
+
 def sait_last_error() -> str:
     return lib().sait_last_error().decode(errors="replace")
 
@@ -367,13 +379,21 @@ class SaitPreconditioner:
         sait_matvec(self.handle, x, y, nrhs, nrhs, int(transpose), stream)
         return y
 
-    def solve(self, b, x=None, transpose=False, restart=30, maxit=10000, rtol=1e-8, flexible=False, stream=None):
+    def set_preconditioner(self, kind="sait", sweeps=1, stream=None):
+        """Preconditioner of later apply / solve calls: "sait" (default),
+        "jacobi" (`sweeps` Jacobi sweeps on L, then on U), "exact" (the
+        triangular solves with L and U) or "none"."""
+        sait_set_preconditioner(self.handle, kind, sweeps, stream)
+
+    def solve(self, b, x=None, transpose=False, restart=30, maxit=10000, rtol=1e-8, flexible=False, stream=None,
+              method="gmres"):
         import torch
 
         if x is None:
             x = torch.zeros_like(b)
         nrhs = 1 if b.dim() == 1 else b.shape[1]
-        o = default_solve_opts(restart=restart, maxit=maxit, rtol=rtol, flexible=int(bool(flexible)))
+        o = default_solve_opts(restart=restart, maxit=maxit, rtol=rtol, flexible=int(bool(flexible)),
+                               method={"gmres": SAIT_METHOD_GMRES, "pcg": SAIT_METHOD_PCG}[method])
         st, infos = sait_solve(self.handle, b, x, nrhs, nrhs, int(transpose), o, self.nsys * nrhs, stream)
         return x, [SolveResult(**i) for i in infos]
 
