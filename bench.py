@@ -14,7 +14,10 @@ wall time, systems/s, pair-iterations/s and the modelled bytes per second
 (batched_bytes).  `other_workloads`: FP64 apply GB/s on the random
 diagonally dominant matrices and on the 2D convection-diffusion factors
 (also after a cache-evicting write), and the forward / adjoint solve times
-of the differentiable 512^2 workload.
+of the differentiable 512^2 workload.  `paper_experiment`: the paper's
+PCG experiment (3D Laplace 100^3, level-0 ILU, 1e-10) with the SAIT
+preconditioners of its tables, 1..15 Jacobi sweeps, the exact triangular
+solves and no preconditioner: iterations and seconds per solve.
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -301,6 +304,63 @@ def extra_workloads(torch, dev):
     return out
 
 
+def paper_experiment(torch, dev):
+    """The paper's 3D experiment (Sec. 4) on one MI355X: 7-point Laplace on
+    the 100^3 interior of a 102^3 mesh, level-0 ILU, PCG to 1e-10 with
+    SAIT_Thr(0.05 / 0.02 / 0.01, 10), SAIT_Pat(1 / 2 / 3, 10), 1..15 Jacobi
+    sweeps per factor, the exact triangular solves and no preconditioner;
+    f ~ U[0, 1) (seed 0).  Iterations and wall time per solve (build
+    excluded, reported apart); the paper's printed iteration counts beside."""
+    from paper_2106_12836_amd import SaitPreconditioner
+    from workloads import poisson3d
+
+    A = poisson3d(100)
+    f = torch.tensor(np.random.default_rng(0).uniform(0.0, 1.0, A.n), dtype=torch.float64, device=dev)
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_table_pcg_iterations.json")))["level0"]
+    printed = {("thr", t): it for t, m, it in golden["sait_thr"]}
+    printed.update({("pat", q): it for q, m, it in golden["sait_pat"]})
+    printed_jac = dict(golden["jacobi"])
+
+    def timed_pcg(pre):
+        pre.solve(f, rtol=1e-10, method="pcg")  # warm-up: allocates the PCG vectors
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, (info,) = pre.solve(f, rtol=1e-10, method="pcg")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, info
+
+    out = dict(workload="3D 7-point Laplace 100^3 (n = 10^6), level-0 ILU, PCG to 1e-10, f ~ U[0,1) (seed 0)",
+               sait=[], jacobi=[], exact=None, none=None)
+    for kind, param in (("thr", 0.05), ("thr", 0.02), ("thr", 0.01), ("pat", 1), ("pat", 2), ("pat", 3)):
+        opts = dict(m=10, tau=param) if kind == "thr" else dict(m=10, pattern_p=param)
+        t0 = time.time()
+        pre = SaitPreconditioner(A, **opts)
+        torch.cuda.synchronize()
+        tb = time.time() - t0
+        q = pre.query()
+        ts, info = timed_pcg(pre)
+        out["sait"].append(dict(preconditioner=f"SAIT_{'Thr' if kind == 'thr' else 'Pat'}({param}, 10)",
+                                ratio_L=round(q["ratio_L"], 4), ratio_U=round(q["ratio_U"], 4),
+                                iterations=info.iterations, seconds=round(ts, 4), build_s=round(tb, 3),
+                                status=info.status, true_relres=info.true_relres,
+                                paper_iterations=printed[(kind, param)]))
+        if kind == "thr" and param == 0.05:
+            for sw in range(1, 16):
+                pre.set_preconditioner("jacobi", sw)
+                ts, info = timed_pcg(pre)
+                out["jacobi"].append(dict(sweeps=sw, iterations=info.iterations, seconds=round(ts, 4),
+                                          status=info.status, paper_iterations=printed_jac[sw]))
+            pre.set_preconditioner("exact")
+            ts, info = timed_pcg(pre)
+            out["exact"] = dict(iterations=info.iterations, seconds=round(ts, 4), status=info.status)
+            pre.set_preconditioner("none")
+            ts, info = timed_pcg(pre)
+            out["none"] = dict(iterations=info.iterations, seconds=round(ts, 4), status=info.status)
+        pre.close()
+        print(f"[bench] paper experiment: {out['sait'][-1]}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,6 +372,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default kernel shapes")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 256-system solve")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (rdd, c2, c5)")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's PCG experiment (100^3)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched solve and print its record (for profiling that launch)")
     args = ap.parse_args()
@@ -429,6 +490,10 @@ def main():
     if not args.no_extra:
         extra = extra_workloads(torch, dev)
 
+    paper = None
+    if not args.no_paper:
+        paper = paper_experiment(torch, dev)
+
     batched = None
     if not args.no_batched:
         print("[bench] batched solve (256 systems x 8 RHS) ...", file=sys.stderr, flush=True)
@@ -466,6 +531,7 @@ def main():
         "time_to_residual": ttr,
         "batched": batched,
         "other_workloads": extra,
+        "paper_experiment": paper,
     }
     print(json.dumps(line), flush=True)
 
