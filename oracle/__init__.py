@@ -53,6 +53,7 @@ def lib():
         pp_d = C.POINTER(_f64p)
         L.or_ilu0.argtypes = [I64, _i32p, _i32p, _f64p, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_ilut.argtypes = [I64, _i32p, _i32p, _f64p, D, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
+        L.or_iluk.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_lower_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_upper_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_sait_step.argtypes = [I64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, D, C.c_int, pp_i, pp_i, pp_d]
@@ -135,6 +136,15 @@ def ilut(A: Csr, tau: float, p: int):
     Lo, Uo = _out3(), _out3()
     st = lib().or_ilut(A.n, rp, ci, v, float(tau), int(p), *(C.byref(x) for x in Lo), *(C.byref(x) for x in Uo))
     _check(st, "ilut")
+    return _take(A.n, *Lo), _take(A.n, *Uo)
+
+
+def iluk(A: Csr, p: int):
+    """ILU(p) by levels of fill: the ILU(0) elimination on the level-p pattern."""
+    keep, (rp, ci, v) = _csr_args(A)
+    Lo, Uo = _out3(), _out3()
+    st = lib().or_iluk(A.n, rp, ci, v, int(p), *(C.byref(x) for x in Lo), *(C.byref(x) for x in Uo))
+    _check(st, "iluk")
     return _take(A.n, *Lo), _take(A.n, *Uo)
 
 

@@ -206,6 +206,130 @@ int or_ilu0(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
 }
 
 /* ------------------------------------------------------------------ */
+/* ILU(p) by levels of fill ("level-1 ILU" of Sec. 4; Saad, ILU(p)):    */
+/* lev(a_ij) = 0 on the pattern of A; eliminating a_ik (k < i, in       */
+/* increasing k) creates (i, j) for every j > k of row k of U with      */
+/* level lev_ik + lev_kj + 1, kept when <= p.  The factors are the      */
+/* ILU(0) elimination on that pattern (A's values, zeros at the fill).  */
+/* ------------------------------------------------------------------ */
+static void heap_push(int32_t *h, int64_t *cnt, int32_t x) {
+    int64_t i = (*cnt)++;
+    h[i] = x;
+    while (i > 0 && h[(i - 1) / 2] > h[i]) {
+        int32_t t = h[i]; h[i] = h[(i - 1) / 2]; h[(i - 1) / 2] = t;
+        i = (i - 1) / 2;
+    }
+}
+
+static int32_t heap_pop(int32_t *h, int64_t *cnt) {
+    int32_t top = h[0];
+    h[0] = h[--(*cnt)];
+    int64_t i = 0;
+    for (;;) {
+        int64_t l = 2 * i + 1, r = l + 1, m = i;
+        if (l < *cnt && h[l] < h[m]) m = l;
+        if (r < *cnt && h[r] < h[m]) m = r;
+        if (m == i) break;
+        int32_t t = h[i]; h[i] = h[m]; h[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+int or_iluk(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int p,
+            int32_t **Lrp, int32_t **Lci, double **Lv,
+            int32_t **Urp, int32_t **Uci, double **Uv) {
+    if (p < 0) return OR_E_INVALID;
+    const int INF = 0x7fffffff;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int *lev = (int *)malloc(sizeof(int) * nn);
+    int32_t *heap = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int32_t *act = (int32_t *)malloc(sizeof(int32_t) * nn);
+    /* levels of the U part (columns > i) of every finished row */
+    int64_t ucap = rp[n] + 16, ucnt = 0;
+    int64_t *uptr = (int64_t *)malloc(sizeof(int64_t) * (nn + 1));
+    int32_t *ucol = (int32_t *)malloc(sizeof(int32_t) * (size_t)ucap);
+    int *ulev = (int *)malloc(sizeof(int) * (size_t)ucap);
+    /* extended pattern */
+    int64_t ecap = rp[n] + 16, ecnt = 0;
+    int32_t *erp = (int32_t *)malloc(sizeof(int32_t) * (nn + 1));
+    int32_t *eci = (int32_t *)malloc(sizeof(int32_t) * (size_t)ecap);
+    double *ev = (double *)malloc(sizeof(double) * (size_t)ecap);
+    double *wv = (double *)calloc(nn, sizeof(double));
+    int st = OR_OK;
+    if (!lev || !heap || !act || !uptr || !ucol || !ulev || !erp || !eci || !ev || !wv) { st = OR_E_NOMEM; goto out; }
+    for (int64_t j = 0; j < n; j++) lev[j] = INF;
+    uptr[0] = 0;
+    erp[0] = 0;
+    for (int64_t i = 0; i < n && st == OR_OK; i++) {
+        int64_t na = 0, nh = 0;
+        for (int64_t q = rp[i]; q < rp[i + 1]; q++) {
+            int32_t j = ci[q];
+            lev[j] = 0;
+            wv[j] = v[q];
+            act[na++] = j;
+            if (j < i) heap_push(heap, &nh, j);
+        }
+        while (nh > 0) {
+            int32_t k = heap_pop(heap, &nh);
+            for (int64_t q = uptr[k]; q < uptr[k + 1]; q++) {
+                int32_t j = ucol[q];
+                int nl = lev[k] + ulev[q] + 1;
+                if (nl > p) continue;
+                if (lev[j] == INF) {
+                    lev[j] = nl;
+                    wv[j] = 0.0;
+                    act[na++] = j;
+                    if (j < i) heap_push(heap, &nh, j);
+                } else if (nl < lev[j]) {
+                    lev[j] = nl;
+                }
+            }
+        }
+        /* sort the row's columns (insertion sort: rows are short) */
+        for (int64_t a = 1; a < na; a++) {
+            int32_t x = act[a];
+            int64_t b = a - 1;
+            while (b >= 0 && act[b] > x) { act[b + 1] = act[b]; b--; }
+            act[b + 1] = x;
+        }
+        if (ecnt + na > ecap || ucnt + na > ucap) {
+            int64_t nc = 2 * (ecap > ucap ? ecap : ucap) + na;
+            int32_t *t1 = (int32_t *)realloc(eci, sizeof(int32_t) * (size_t)nc);
+            double *t2 = (double *)realloc(ev, sizeof(double) * (size_t)nc);
+            int32_t *t3 = (int32_t *)realloc(ucol, sizeof(int32_t) * (size_t)nc);
+            int *t4 = (int *)realloc(ulev, sizeof(int) * (size_t)nc);
+            if (t1) eci = t1;
+            if (t2) ev = t2;
+            if (t3) ucol = t3;
+            if (t4) ulev = t4;
+            if (!t1 || !t2 || !t3 || !t4) { st = OR_E_NOMEM; break; }
+            ecap = ucap = nc;
+        }
+        for (int64_t a = 0; a < na; a++) {
+            int32_t j = act[a];
+            eci[ecnt] = j;
+            ev[ecnt] = wv[j];
+            ecnt++;
+            if (j > i) {
+                ucol[ucnt] = j;
+                ulev[ucnt] = lev[j];
+                ucnt++;
+            }
+            lev[j] = INF;
+            wv[j] = 0.0;
+        }
+        erp[i + 1] = (int32_t)ecnt;
+        uptr[i + 1] = ucnt;
+    }
+    if (st == OR_OK) st = or_ilu0(n, erp, eci, ev, Lrp, Lci, Lv, Urp, Uci, Uv);
+out:
+    free(lev); free(heap); free(act); free(uptr); free(ucol); free(ulev);
+    free(erp); free(eci); free(ev); free(wv);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
 /* ILUT(tau, p): Saad Alg. 10.6 (dual threshold).                       */
 /* ------------------------------------------------------------------ */
 int or_ilut(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
