@@ -56,9 +56,10 @@ def lib():
         L.or_iluk.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_lower_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_upper_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
-        L.or_sait_step.argtypes = [I64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, D, C.c_int, pp_i, pp_i, pp_d]
-        L.or_sait_thr.argtypes = [I64, _i32p, _i32p, _f64p, D, C.c_int, C.c_int, pp_i, pp_i, pp_d]
-        L.or_sait_pat.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, C.c_int, pp_i, pp_i, pp_d]
+        L.or_sait_step.argtypes = [I64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, D, C.c_int, C.c_int, pp_i, pp_i,
+                                   pp_d]
+        L.or_sait_thr.argtypes = [I64, _i32p, _i32p, _f64p, D, C.c_int, C.c_int, C.c_int, pp_i, pp_i, pp_d]
+        L.or_sait_pat.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, C.c_int, C.c_int, pp_i, pp_i, pp_d]
         L.or_spmv.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_spmv.restype = None
         L.or_apply.argtypes = [I64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p]
@@ -164,30 +165,51 @@ def upper_solve(U: Csr, b):
     return x
 
 
-def sait_step(T: Csr, M: Csr, tau: float, cap: int = 0) -> Csr:
-    """One unscaled pass: drop(T~ M + I)."""
+def _side(side: str) -> int:
+    if side not in ("left", "right"):
+        raise ValueError("side must be 'left' (T~ M) or 'right' (M T~)")
+    return int(side == "right")
+
+
+def sait_step(T: Csr, M: Csr, tau: float, cap: int = 0, side: str = "left") -> Csr:
+    """One unscaled pass: drop(T~ M + I), or drop(M T~ + I) with side="right"."""
     k1, (trp, tci, tv) = _csr_args(T)
     k2, (mrp, mci, mv) = _csr_args(M)
     O = _out3()
-    st = lib().or_sait_step(T.n, trp, tci, tv, mrp, mci, mv, float(tau), int(cap), *(C.byref(x) for x in O))
+    st = lib().or_sait_step(T.n, trp, tci, tv, mrp, mci, mv, float(tau), int(cap), _side(side),
+                            *(C.byref(x) for x in O))
     _check(st, "sait_step")
     return _take(T.n, *O)
 
 
-def sait_thr(T: Csr, tau: float, m: int, cap: int = 0) -> Csr:
-    """SAIT_Thr(tau, m) (Alg. 2), optional per-row cap."""
+def sait_thr(T: Csr, tau: float, m: int, cap: int = 0, side: str = "left") -> Csr:
+    """SAIT_Thr(tau, m) (Alg. 2), optional per-row cap; side="right" runs
+    every pass as M T~ + I."""
     keep, (rp, ci, v) = _csr_args(T)
     O = _out3()
-    _check(lib().or_sait_thr(T.n, rp, ci, v, float(tau), int(m), int(cap), *(C.byref(x) for x in O)), "sait_thr")
+    _check(lib().or_sait_thr(T.n, rp, ci, v, float(tau), int(m), int(cap), _side(side), *(C.byref(x) for x in O)),
+           "sait_thr")
     return _take(T.n, *O)
 
 
-def sait_pat(T: Csr, p: int, m: int) -> Csr:
-    """SAIT_Pat(p, m) (Alg. 3)."""
+def sait_pat(T: Csr, p: int, m: int, side: str = "left") -> Csr:
+    """SAIT_Pat(p, m) (Alg. 3); side="right" runs every pass as M T~ + I."""
     keep, (rp, ci, v) = _csr_args(T)
     O = _out3()
-    _check(lib().or_sait_pat(T.n, rp, ci, v, int(p), int(m), *(C.byref(x) for x in O)), "sait_pat")
+    _check(lib().or_sait_pat(T.n, rp, ci, v, int(p), int(m), _side(side), *(C.byref(x) for x in O)), "sait_pat")
     return _take(T.n, *O)
+
+
+def sait_factors(L: Csr, U: Csr, m: int, tau: float = 0.0, cap: int = 0, p: int = -1,
+                 upper_side: str = "right"):
+    """(M_L, M_U) of an ILU pair: M_L by the left-multiplied recursion of
+    Alg. 1, M_U by the recursion multiplied from the right (the default; for
+    a symmetric A this gives M_U = M_L^T D^-1 and a symmetric positive
+    definite M_U M_L) or from the left (upper_side="left", Alg. 1 verbatim).
+    p >= 0 selects SAIT_Pat(p, m), else SAIT_Thr(tau, m) with the cap."""
+    if p >= 0:
+        return sait_pat(L, p, m), sait_pat(U, p, m, side=upper_side)
+    return sait_thr(L, tau, m, cap), sait_thr(U, tau, m, cap, side=upper_side)
 
 
 def identity(n: int) -> Csr:

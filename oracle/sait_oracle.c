@@ -469,16 +469,27 @@ static int sait_dinv(int64_t n, const int32_t *rp, const int32_t *ci, const doub
 
 /*
  * One pass of the Horner recursion (Eq. Recursive) with dropping:
- *     W = T~ * Mprev + I,   T~ = I - D^-1 T   (diagonal structurally zero)
- * then keep (i,j) iff |W_ij| > tau (Alg. 2 / Appendix A mask) -- or iff
- * (i,j) lies in the pattern S when S is given (Alg. 3) -- and finally, if
- * cap > 0, keep the diagonal plus the cap-1 largest |W_ij|.
- * Row i of T~*M is formed the Gustavson way: for each l in T~ row i in
- * increasing column order, add T~_il * M_l,* into a dense accumulator.
- * Pattern mode (S != NULL): keep iff W_ij != 0 and (i,j) in S.
+ *     W = T~ * Mprev + I   (right == 0, Alg. 1 step 3 as printed), or
+ *     W = Mprev * T~ + I   (right == 1),   T~ = I - D^-1 T
+ * (diagonal of T~ structurally zero).  Both sides give the same truncated
+ * Neumann sum when nothing is dropped, since the polynomial in T~ commutes
+ * with T~; with dropping they differ.  Multiplying from the right for the
+ * upper factor U of a symmetric A (U = D L^T, so T~_U = T~_L^T) makes the
+ * upper factor the transpose of the lower one, M_U = M_L^T D^-1, and
+ * M_U M_L symmetric positive definite, as the PCG experiments of Sec. 4
+ * need.  Then keep (i,j) iff |W_ij| > tau (Alg. 2 / Appendix A mask) -- or
+ * iff (i,j) lies in the pattern S when S is given (Alg. 3) -- and finally,
+ * if cap > 0, keep the diagonal plus the cap-1 largest |W_ij|.
+ * Row i of W is formed the Gustavson way into a dense accumulator:
+ *   left:  for each l in T~ row i in increasing column order, add
+ *          T~_il * M_l,*;
+ *   right: for each l in M row i in increasing column order, add
+ *          M_il * T~_l,*.
+ * Either way every W_ij sums its products in increasing l, then adds the
+ * identity.  Pattern mode (S != NULL): keep iff W_ij != 0 and (i,j) in S.
  */
 static int sait_pass(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
-                     const double *dinv,
+                     const double *dinv, int right,
                      const int32_t *Mrp, const int32_t *Mci, const double *Mv,
                      double tau, int cap,
                      const int32_t *Srp, const int32_t *Sci,
@@ -486,14 +497,28 @@ static int sait_pass(int64_t n, const int32_t *Trp, const int32_t *Tci, const do
                      or_builder *out) {
     for (int64_t i = 0; i < n; i++) {
         int64_t nl = 0;
-        for (int64_t p = Trp[i]; p < Trp[i + 1]; p++) {
-            int64_t l = Tci[p];
-            if (l == i) continue;                       /* T~_ii = 0 */
-            double tl = -(dinv[i] * Tv[p]);             /* T~_il */
-            for (int64_t q = Mrp[l]; q < Mrp[l + 1]; q++) {
-                int32_t j = Mci[q];
-                if (!touched[j]) { touched[j] = 1; acc[j] = 0.0; list[nl++] = j; }
-                acc[j] = acc[j] + tl * Mv[q];
+        if (!right) {
+            for (int64_t p = Trp[i]; p < Trp[i + 1]; p++) {
+                int64_t l = Tci[p];
+                if (l == i) continue;                       /* T~_ii = 0 */
+                double tl = -(dinv[i] * Tv[p]);             /* T~_il */
+                for (int64_t q = Mrp[l]; q < Mrp[l + 1]; q++) {
+                    int32_t j = Mci[q];
+                    if (!touched[j]) { touched[j] = 1; acc[j] = 0.0; list[nl++] = j; }
+                    acc[j] = acc[j] + tl * Mv[q];
+                }
+            }
+        } else {
+            for (int64_t p = Mrp[i]; p < Mrp[i + 1]; p++) {
+                int64_t l = Mci[p];
+                double ml = Mv[p];                          /* M_il */
+                for (int64_t q = Trp[l]; q < Trp[l + 1]; q++) {
+                    int32_t j = Tci[q];
+                    if (j == l) continue;                   /* T~_ll = 0 */
+                    double tlj = -(dinv[l] * Tv[q]);        /* T~_lj */
+                    if (!touched[j]) { touched[j] = 1; acc[j] = 0.0; list[nl++] = j; }
+                    acc[j] = acc[j] + ml * tlj;
+                }
             }
         }
         /* + I */
@@ -555,10 +580,10 @@ static void ws_free(sait_ws *w) {
 }
 
 /* One unscaled pass, exported for step-by-step comparison:
- * Mnext = drop(T~ * Mprev + I). */
+ * Mnext = drop(T~ * Mprev + I), or drop(Mprev * T~ + I) when right != 0. */
 int or_sait_step(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
                  const int32_t *Mrp, const int32_t *Mci, const double *Mv,
-                 double tau, int cap,
+                 double tau, int cap, int right,
                  int32_t **Orp, int32_t **Oci, double **Ov) {
     if (!(tau >= 0.0 && tau < 1.0) || cap < 0) return OR_E_INVALID;
     sait_ws w;
@@ -567,7 +592,7 @@ int or_sait_step(int64_t n, const int32_t *Trp, const int32_t *Tci, const double
     if (st == OR_OK) st = sait_dinv(n, Trp, Tci, Tv, w.dinv);
     if (st == OR_OK) st = bld_init(&out, n, Mrp[n] + n);
     if (st == OR_OK) {
-        st = sait_pass(n, Trp, Tci, Tv, w.dinv, Mrp, Mci, Mv, tau, cap, NULL, NULL,
+        st = sait_pass(n, Trp, Tci, Tv, w.dinv, right, Mrp, Mci, Mv, tau, cap, NULL, NULL,
                        w.acc, w.touched, w.list, w.inS, w.ent, &out);
         if (st == OR_OK) bld_give(&out, Orp, Oci, Ov);
         else bld_free(&out);
@@ -578,7 +603,7 @@ int or_sait_step(int64_t n, const int32_t *Trp, const int32_t *Tci, const double
 
 /* Common driver for Alg. 2 (S == NULL after p passes: threshold) and Alg. 3. */
 static int sait_run(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
-                    double tau, int m, int cap, int p_pattern,
+                    double tau, int m, int cap, int p_pattern, int right,
                     int32_t **Orp, int32_t **Oci, double **Ov) {
     sait_ws w;
     int st = ws_init(&w, n);
@@ -593,7 +618,7 @@ static int sait_run(int64_t n, const int32_t *Trp, const int32_t *Tci, const dou
     for (int k = 0; k < p_pattern && st == OR_OK; k++) {
         or_builder nxt;
         st = bld_init(&nxt, n, cur.nnz + n);
-        if (st == OR_OK) st = sait_pass(n, Trp, Tci, Tv, w.dinv, cur.rp, cur.ci, cur.v, 0.0, 0,
+        if (st == OR_OK) st = sait_pass(n, Trp, Tci, Tv, w.dinv, right, cur.rp, cur.ci, cur.v, 0.0, 0,
                                         NULL, NULL, w.acc, w.touched, w.list, w.inS, w.ent, &nxt);
         bld_free(&cur);
         cur = nxt;
@@ -611,7 +636,7 @@ static int sait_run(int64_t n, const int32_t *Trp, const int32_t *Tci, const dou
     for (int k = 0; k < m && st == OR_OK; k++) {
         or_builder nxt;
         st = bld_init(&nxt, n, cur.nnz + n);
-        if (st == OR_OK) st = sait_pass(n, Trp, Tci, Tv, w.dinv, cur.rp, cur.ci, cur.v, tau, cap,
+        if (st == OR_OK) st = sait_pass(n, Trp, Tci, Tv, w.dinv, right, cur.rp, cur.ci, cur.v, tau, cap,
                                         Srp, Sci, w.acc, w.touched, w.list, w.inS, w.ent, &nxt);
         bld_free(&cur);
         cur = nxt;
@@ -628,21 +653,22 @@ static int sait_run(int64_t n, const int32_t *Trp, const int32_t *Tci, const dou
     return st;
 }
 
-/* SAIT_Thr(tau, m) with optional per-row cap (Alg. 2; Appendix A). */
+/* SAIT_Thr(tau, m) with optional per-row cap (Alg. 2; Appendix A);
+ * right != 0 multiplies T~ from the right in every pass. */
 int or_sait_thr(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
-                double tau, int m, int cap,
+                double tau, int m, int cap, int right,
                 int32_t **Orp, int32_t **Oci, double **Ov) {
     if (!(tau >= 0.0 && tau < 1.0) || m < 0 || cap < 0) return OR_E_INVALID;
-    return sait_run(n, Trp, Tci, Tv, tau, m, cap, -1, Orp, Oci, Ov);
+    return sait_run(n, Trp, Tci, Tv, tau, m, cap, -1, right, Orp, Oci, Ov);
 }
 
 /* SAIT_Pat(p, m) (Alg. 3): p passes without dropping fix the pattern S of
  * T^p (= pattern of M_{p+1} in Eq. M_poly), m further passes masked to S. */
 int or_sait_pat(int64_t n, const int32_t *Trp, const int32_t *Tci, const double *Tv,
-                int p, int m,
+                int p, int m, int right,
                 int32_t **Orp, int32_t **Oci, double **Ov) {
     if (p < 0 || m < 0) return OR_E_INVALID;
-    return sait_run(n, Trp, Tci, Tv, 0.0, m, 0, p, Orp, Oci, Ov);
+    return sait_run(n, Trp, Tci, Tv, 0.0, m, 0, p, right, Orp, Oci, Ov);
 }
 
 /* ------------------------------------------------------------------ */

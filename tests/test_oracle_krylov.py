@@ -19,7 +19,7 @@ from workloads import Csr, config, grf_diffusion2d, poisson2d, poisson3d, random
 
 def _factors(orc, A, tau=1e-2, m=3):
     L, U = orc.ilu0(A)
-    return L, U, orc.sait_thr(L, tau, m), orc.sait_thr(U, tau, m)
+    return (L, U, *orc.sait_factors(L, U, m, tau=tau))
 
 
 def test_apply_f64_matches_scipy(orc):
@@ -78,7 +78,7 @@ def test_gmres_identity_and_exact_preconditioner(orc):
     # tridiagonal A: ILU(0) = exact LU and SAIT(0, n-1) = exact inverses
     A = Csr.from_scipy(sp.diags([-np.ones(n - 1), 3 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr"))
     L, U = orc.ilu0(A)
-    ML, MU = orc.sait_thr(L, 0.0, n - 1), orc.sait_thr(U, 0.0, n - 1)
+    ML, MU = orc.sait_factors(L, U, n - 1, tau=0.0)
     out = orc.gmres(A, b, ("sait64", ML, MU), restart=10, rtol=1e-10)
     assert out["iters"] == 1 and out["relres"] < 1e-12
     out = orc.gmres(A, b, ("exact", L, U), restart=10, rtol=1e-10)

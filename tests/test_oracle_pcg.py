@@ -7,7 +7,10 @@ triangular solve; PCG terminates in one step with the exact preconditioner
 or A = I and in d steps on a diagonal with d distinct values, minimises the
 A-norm error over the Krylov space, matches scipy's CG, and reproduces the
 iteration counts the paper prints for its 100^3 experiment (within 5 %:
-the right-hand side is not printed)."""
+the right-hand side is not printed), with level-0 and level-1 ILU factors.
+The level-1 SAIT_Thr(0.02, 10) row also fixes the side of the upper
+factor's recursion: with M_U from T~ M + I (Alg. 1 verbatim) PCG needs
+thousands of iterations; with M T~ + I it needs about the printed 133."""
 
 import json
 import os
@@ -147,8 +150,27 @@ def test_paper_sait_iterations(paper_factors, kind, param):
     g = json.load(open(os.path.join(HERE, "golden", "paper_table_pcg_iterations.json")))["level0"]
     printed = {p: it for p, m, it in g["sait_thr" if kind == "thr" else "sait_pat"]}[param]
     if kind == "thr":
-        ML, MU = oracle.sait_thr(L, param, 10), oracle.sait_thr(U, param, 10)
+        ML, MU = oracle.sait_factors(L, U, 10, tau=param)
     else:
-        ML, MU = oracle.sait_pat(L, param, 10), oracle.sait_pat(U, param, 10)
+        ML, MU = oracle.sait_factors(L, U, 10, p=param)
     out = oracle.pcg(A, f, ("sait64", ML, MU), rtol=1e-10)
+    assert out["status"] == 0 and _within(out["iters"], printed), (out["iters"], printed)
+
+
+
+@pytest.mark.parametrize("sweeps", [1, 4, 10])
+def test_paper_jacobi_iterations_level1(paper_level1, sweeps):
+    P = paper_level1
+    printed = dict(json.load(open(os.path.join(HERE, "golden", "paper_table_pcg_iterations.json")))
+                   ["level1"]["jacobi"])[sweeps]
+    out = oracle.pcg(P.A, P.f, ("jacobi", P.L, P.U, sweeps), rtol=1e-10)
+    assert out["status"] == 0 and _within(out["iters"], printed), (out["iters"], printed)
+
+
+@pytest.mark.parametrize("kind,param", [("thr", 0.02), ("pat", 2)])
+def test_paper_sait_iterations_level1(paper_level1, kind, param):
+    P = paper_level1
+    g = json.load(open(os.path.join(HERE, "golden", "paper_table_pcg_iterations.json")))["level1"]
+    printed = {p: it for p, m, it in g["sait_thr" if kind == "thr" else "sait_pat"]}[param]
+    out = oracle.pcg(P.A, P.f, ("sait64", *P.sait(kind, param)), rtol=1e-10)
     assert out["status"] == 0 and _within(out["iters"], printed), (out["iters"], printed)
