@@ -115,7 +115,7 @@ def cpu_baseline(A, tau, m, target_seconds=12.0):
 
     t0 = time.time()
     L, U = oracle.ilu0(A)
-    ML, MU = oracle.sait_thr(L, tau, m), oracle.sait_thr(U, tau, m)
+    ML, MU = oracle.sait_factors(L, U, m, tau=tau)
     t_build = time.time() - t0
     r = np.random.default_rng(11).uniform(-1, 1, A.n)
     oracle.apply(ML, MU, r)  # warm
@@ -306,20 +306,18 @@ def extra_workloads(torch, dev):
 
 def paper_experiment(torch, dev):
     """The paper's 3D experiment (Sec. 4) on one MI355X: 7-point Laplace on
-    the 100^3 interior of a 102^3 mesh, level-0 ILU, PCG to 1e-10 with
-    SAIT_Thr(0.05 / 0.02 / 0.01, 10), SAIT_Pat(1 / 2 / 3, 10), 1..15 Jacobi
-    sweeps per factor, the exact triangular solves and no preconditioner;
-    f ~ U[0, 1) (seed 0).  Iterations and wall time per solve (build
-    excluded, reported apart); the paper's printed iteration counts beside."""
+    the 100^3 interior of a 102^3 mesh, level-0 and level-1 ILU, PCG to
+    1e-10 with SAIT_Thr(0.05 / 0.02 / 0.01, 10), SAIT_Pat(1 / 2 / 3, 10),
+    1..15 Jacobi sweeps per factor, the exact triangular solves and no
+    preconditioner; f ~ U[0, 1) (seed 0).  Iterations and wall time per
+    solve (build excluded, reported apart); the paper's printed iteration
+    counts beside."""
     from paper_2106_12836_amd import SaitPreconditioner
     from workloads import poisson3d
 
     A = poisson3d(100)
     f = torch.tensor(np.random.default_rng(0).uniform(0.0, 1.0, A.n), dtype=torch.float64, device=dev)
-    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_table_pcg_iterations.json")))["level0"]
-    printed = {("thr", t): it for t, m, it in golden["sait_thr"]}
-    printed.update({("pat", q): it for q, m, it in golden["sait_pat"]})
-    printed_jac = dict(golden["jacobi"])
+    golden_all = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_table_pcg_iterations.json")))
 
     def timed_pcg(pre):
         pre.solve(f, rtol=1e-10, method="pcg")  # warm-up: allocates the PCG vectors
@@ -329,35 +327,44 @@ def paper_experiment(torch, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, info
 
-    out = dict(workload="3D 7-point Laplace 100^3 (n = 10^6), level-0 ILU, PCG to 1e-10, f ~ U[0,1) (seed 0)",
-               sait=[], jacobi=[], exact=None, none=None)
-    for kind, param in (("thr", 0.05), ("thr", 0.02), ("thr", 0.01), ("pat", 1), ("pat", 2), ("pat", 3)):
-        opts = dict(m=10, tau=param) if kind == "thr" else dict(m=10, pattern_p=param)
-        t0 = time.time()
-        pre = SaitPreconditioner(A, **opts)
-        torch.cuda.synchronize()
-        tb = time.time() - t0
-        q = pre.query()
-        ts, info = timed_pcg(pre)
-        out["sait"].append(dict(preconditioner=f"SAIT_{'Thr' if kind == 'thr' else 'Pat'}({param}, 10)",
-                                ratio_L=round(q["ratio_L"], 4), ratio_U=round(q["ratio_U"], 4),
-                                iterations=info.iterations, seconds=round(ts, 4), build_s=round(tb, 3),
-                                status=info.status, true_relres=info.true_relres,
-                                paper_iterations=printed[(kind, param)]))
-        if kind == "thr" and param == 0.05:
-            for sw in range(1, 16):
-                pre.set_preconditioner("jacobi", sw)
+    out = dict(workload="3D 7-point Laplace 100^3 (n = 10^6), level-0 / level-1 ILU, PCG to 1e-10, "
+                        "f ~ U[0,1) (seed 0)")
+    for level in (0, 1):
+        golden = golden_all[f"level{level}"]
+        printed = {("thr", t): it for t, m, it in golden["sait_thr"]}
+        printed.update({("pat", q): it for q, m, it in golden["sait_pat"]})
+        printed_jac = dict(golden["jacobi"])
+        ilu = {} if level == 0 else dict(ilu_kind="iluk", ilu_level=1)
+        rec = dict(sait=[], jacobi=[], exact=None, none=None)
+        for kind, param in (("thr", 0.05), ("thr", 0.02), ("thr", 0.01), ("pat", 1), ("pat", 2), ("pat", 3)):
+            opts = dict(m=10, tau=param) if kind == "thr" else dict(m=10, pattern_p=param)
+            t0 = time.time()
+            pre = SaitPreconditioner(A, **opts, **ilu)
+            torch.cuda.synchronize()
+            tb = time.time() - t0
+            q = pre.query()
+            ts, info = timed_pcg(pre)
+            rec["sait"].append(dict(preconditioner=f"SAIT_{'Thr' if kind == 'thr' else 'Pat'}({param}, 10)",
+                                    ratio_L=round(q["ratio_L"], 4), ratio_U=round(q["ratio_U"], 4),
+                                    iterations=info.iterations, seconds=round(ts, 4), build_s=round(tb, 3),
+                                    status=info.status, true_relres=info.true_relres,
+                                    paper_iterations=printed[(kind, param)]))
+            if kind == "thr" and param == 0.05:
+                for sw in range(1, 16):
+                    pre.set_preconditioner("jacobi", sw)
+                    ts, info = timed_pcg(pre)
+                    rec["jacobi"].append(dict(sweeps=sw, iterations=info.iterations, seconds=round(ts, 4),
+                                              status=info.status, paper_iterations=printed_jac[sw]))
+                pre.set_preconditioner("exact")
                 ts, info = timed_pcg(pre)
-                out["jacobi"].append(dict(sweeps=sw, iterations=info.iterations, seconds=round(ts, 4),
-                                          status=info.status, paper_iterations=printed_jac[sw]))
-            pre.set_preconditioner("exact")
-            ts, info = timed_pcg(pre)
-            out["exact"] = dict(iterations=info.iterations, seconds=round(ts, 4), status=info.status)
-            pre.set_preconditioner("none")
-            ts, info = timed_pcg(pre)
-            out["none"] = dict(iterations=info.iterations, seconds=round(ts, 4), status=info.status)
-        pre.close()
-        print(f"[bench] paper experiment: {out['sait'][-1]}", file=sys.stderr, flush=True)
+                rec["exact"] = dict(iterations=info.iterations, seconds=round(ts, 4), status=info.status)
+                if level == 0:
+                    pre.set_preconditioner("none")
+                    ts, info = timed_pcg(pre)
+                    out["none"] = dict(iterations=info.iterations, seconds=round(ts, 4), status=info.status)
+            pre.close()
+            print(f"[bench] paper experiment, level-{level} ILU: {rec['sait'][-1]}", file=sys.stderr, flush=True)
+        out[f"level{level}"] = rec
     return out
 
 

@@ -54,7 +54,7 @@ enum {
 };
 
 /* Incomplete factorisation feeding SAIT (Sec. 3.1 takes L, U from ILU). */
-enum { SAIT_ILU0 = 0, SAIT_ILUT = 1 };
+enum { SAIT_ILU0 = 0, SAIT_ILUT = 1, SAIT_ILUK = 2 };
 
 /* Storage precision of M_L, M_U values (accumulation is FP64 for SAIT_F64,
  * binary32 otherwise). */
@@ -74,16 +74,27 @@ typedef struct {
 
 /* Build options (sait_default_build_opts fills the defaults in brackets). */
 typedef struct {
-    int ilu_kind;        /* SAIT_ILU0 [default] or SAIT_ILUT */
+    int ilu_kind;        /* SAIT_ILU0 [default], SAIT_ILUT, or SAIT_ILUK (levels of fill, Sec. 4) */
     double ilut_tau;     /* ILUT drop tolerance, relative to ||a_i,*||_2 [1e-3] */
     int ilut_fill;       /* ILUT: keep at most this many off-diagonals per row in each of L, U [10] */
-    int m;               /* number of Horner passes M <- T~ M + I (Alg. 1-3) [3] */
+    int m;               /* number of Horner passes M <- T~ M + I (Alg. 1-3) [3]; for U see upper_side */
     double tau;          /* SAIT_Thr drop tolerance: keep |M_ij| > tau, 0 <= tau < 1 (Alg. 2) [1e-2] */
     int max_nnz_row;     /* optional cap: keep the diagonal and the max_nnz_row-1 largest |M_ij| per row; 0 = off [0] */
     int pattern_p;       /* < 0: threshold dropping (SAIT_Thr) [-1];  >= 0: SAIT_Pat(p, m) (Alg. 3) */
     int precision;       /* SAIT_F64 [default], SAIT_F32 or SAIT_BF16 storage of M_L, M_U */
     int build_transpose; /* also build A^T, M_L^T, M_U^T for transpose solves / gradients [0] */
+    int ilu_level;       /* SAIT_ILUK: keep fill of level <= ilu_level (1: the paper's level-1 ILU) [1] */
+    int upper_side;      /* side of T~ in the passes that build M_U: SAIT_SIDE_RIGHT [default] or SAIT_SIDE_LEFT */
 } sait_build_opts;
+
+/* Side of T~ in a Horner pass.  SAIT_SIDE_LEFT: M <- drop(T~ M + I), Alg. 1
+ * as printed (always used for M_L).  SAIT_SIDE_RIGHT: M <- drop(M T~ + I).
+ * Without dropping both give the same truncated series (the polynomial in
+ * T~ commutes with T~); with dropping they differ.  Right-multiplying for
+ * the upper factor of a symmetric A (U = D L^T) gives M_U = M_L^T D^-1 and
+ * a symmetric positive definite M_U M_L, which the PCG experiments of
+ * Sec. 4 need; it reproduces their level-1 ILU iteration counts. */
+enum { SAIT_SIDE_LEFT = 0, SAIT_SIDE_RIGHT = 1 };
 
 /* Solve options. */
 typedef struct {
@@ -271,7 +282,8 @@ int sait_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
 
 /*
  * Test entry point: one unscaled Horner pass on the device,
- *     M_next = drop(T~ M_prev + I),  T~ = I - D^-1 T   (Eq. Recursive, Alg. 2)
+ *     M_next = drop(T~ M_prev + I)  (side = SAIT_SIDE_LEFT, Eq. Recursive, Alg. 2)
+ *     M_next = drop(M_prev T~ + I)  (side = SAIT_SIDE_RIGHT),  T~ = I - D^-1 T
  * with the threshold rule (tau) and optional cap, for host CSR inputs T
  * (triangular, nonzero diagonal) and M_prev.  Output: host buffers
  * out_row_ptr (n+1), out_col_idx / out_val (capacity entries).  If the
@@ -281,7 +293,7 @@ int sait_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
  */
 int sait_debug_step(int64_t n, const int32_t *T_row_ptr, const int32_t *T_col_idx, const double *T_val,
                     const int32_t *M_row_ptr, const int32_t *M_col_idx, const double *M_val,
-                    double tau, int max_nnz_row, int64_t capacity,
+                    double tau, int max_nnz_row, int side, int64_t capacity,
                     int32_t *out_row_ptr, int32_t *out_col_idx, double *out_val, int64_t *out_nnz);
 
 #ifdef __cplusplus

@@ -192,6 +192,7 @@ extern "C" {
 void sait_default_build_opts(sait_build_opts *o) {
     if (!o) return;
     o->ilu_kind = SAIT_ILU0;
+    o->ilu_level = 1;
     o->ilut_tau = 1e-3;
     o->ilut_fill = 10;
     o->m = 3;
@@ -200,6 +201,7 @@ void sait_default_build_opts(sait_build_opts *o) {
     o->pattern_p = -1;
     o->precision = SAIT_F64;
     o->build_transpose = 0;
+    o->upper_side = SAIT_SIDE_RIGHT;
 }
 
 void sait_default_solve_opts(sait_solve_opts *o) {
@@ -222,7 +224,11 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         sait_build_opts opts;
         sait_default_build_opts(&opts);
         if (o) opts = *o;
-        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT) fail(SAIT_E_INVALID, "unknown ilu_kind");
+        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT && opts.ilu_kind != SAIT_ILUK)
+            fail(SAIT_E_INVALID, "unknown ilu_kind");
+        if (opts.ilu_kind == SAIT_ILUK && opts.ilu_level < 0) fail(SAIT_E_INVALID, "ilu_level must be >= 0");
+        if (opts.upper_side != SAIT_SIDE_LEFT && opts.upper_side != SAIT_SIDE_RIGHT)
+            fail(SAIT_E_INVALID, "upper_side must be SAIT_SIDE_LEFT or SAIT_SIDE_RIGHT");
         if (opts.precision != SAIT_F64 && opts.precision != SAIT_F32 && opts.precision != SAIT_BF16)
             fail(SAIT_E_INVALID, "unknown precision");
         if (!(opts.tau >= 0.0 && opts.tau < 1.0)) fail(SAIT_E_INVALID, "tau must satisfy 0 <= tau < 1");
@@ -262,6 +268,7 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         h->A_h.ci.assign(col_idx, col_idx + row_ptr[n]);
         h->A_h.v.assign(val, val + row_ptr[n]);
         if (opts.ilu_kind == SAIT_ILU0) host_ilu0(h->A_h, h->L_h, h->U_h);
+        else if (opts.ilu_kind == SAIT_ILUK) host_iluk(h->A_h, opts.ilu_level, h->L_h, h->U_h);
         else host_ilut(h->A_h, opts.ilut_tau, opts.ilut_fill, h->L_h, h->U_h);
 
         hipStream_t s = as_stream(hip_stream);
@@ -280,7 +287,9 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         {
             DevCsr T;
             upload_csr(&h->alloc, h->U_h, T, s);
-            build_sait_factor(&h->alloc, T, p, h->MU, s);
+            SaitParams pu = p;
+            pu.right = opts.upper_side == SAIT_SIDE_RIGHT;
+            build_sait_factor(&h->alloc, T, pu, h->MU, s);
         }
         if (opts.build_transpose) {
             transpose_csr(&h->alloc, h->A, h->At, s);
@@ -636,9 +645,10 @@ int sait_copy(const void *src, void *dst, size_t bytes, void *hip_stream) {
 
 int sait_debug_step(int64_t n, const int32_t *T_row_ptr, const int32_t *T_col_idx, const double *T_val,
                     const int32_t *M_row_ptr, const int32_t *M_col_idx, const double *M_val, double tau,
-                    int max_nnz_row, int64_t capacity, int32_t *out_row_ptr, int32_t *out_col_idx, double *out_val,
-                    int64_t *out_nnz) {
+                    int max_nnz_row, int side, int64_t capacity, int32_t *out_row_ptr, int32_t *out_col_idx,
+                    double *out_val, int64_t *out_nnz) {
     return guard([&]() -> int {
+        if (side != SAIT_SIDE_LEFT && side != SAIT_SIDE_RIGHT) fail(SAIT_E_INVALID, "side must be SAIT_SIDE_LEFT or SAIT_SIDE_RIGHT");
         validate_csr(n, T_row_ptr, T_col_idx, T_val, "T");
         validate_csr(n, M_row_ptr, M_col_idx, M_val, "M");
         if (!out_row_ptr || !out_nnz) fail(SAIT_E_INVALID, "null output");
@@ -666,7 +676,7 @@ int sait_debug_step(int64_t n, const int32_t *T_row_ptr, const int32_t *T_col_id
         DevCsr T, M, O;
         upload_csr(&a, Th, T, nullptr);
         upload_csr(&a, Mh, M, nullptr);
-        sait_single_pass(&a, T, M, tau, max_nnz_row, O, nullptr);
+        sait_single_pass(&a, T, M, side == SAIT_SIDE_RIGHT, tau, max_nnz_row, O, nullptr);
         download_csr(O, Oh, nullptr);
         *out_nnz = Oh.nnz();
         std::copy(Oh.rp.begin(), Oh.rp.end(), out_row_ptr);

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <limits>
 #include <queue>
 
 #include "sait_internal.h"
@@ -212,6 +213,69 @@ void host_ilut(const HostCsr &A, double tau, int fill, HostCsr &L, HostCsr &U) {
             in[j] = 0;
         }
     }
+}
+
+
+// ILU(p) by levels of fill ("level-1 ILU", Sec. 4): the level of an entry
+// of A is 0; eliminating (i, k), k < i in increasing order, reaches (i, j)
+// for every j > k of row k of U at level lev(i,k) + lev(k,j) + 1; positions
+// reached at a level <= p form the pattern, and the factors are the ILU(0)
+// elimination over it (A's values there, zeros at the fill positions).
+void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U) {
+    if (level < 0) fail(SAIT_E_INVALID, "ILU(k): level must be >= 0");
+    const int64_t n = A.n;
+    constexpr int kNone = std::numeric_limits<int>::max();
+    std::vector<int> lev(n, kNone);
+    std::vector<int32_t> upos(n + 1, 0);   // U-part (columns > row) levels of finished rows
+    std::vector<int32_t> ucol;
+    std::vector<int> ulev;
+    HostCsr E;                               // A on the level-p pattern
+    E.n = n;
+    E.rp.assign(n + 1, 0);
+    std::vector<int32_t> row;
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> pending;
+    for (int64_t i = 0; i < n; ++i) {
+        row.clear();
+        for (int32_t q = A.rp[i]; q < A.rp[i + 1]; ++q) {
+            const int32_t j = A.ci[q];
+            lev[j] = 0;
+            row.push_back(j);
+            if (j < i) pending.push(j);
+        }
+        while (!pending.empty()) {
+            const int32_t k = pending.top();
+            pending.pop();
+            const int lk = lev[k];
+            for (int32_t q = upos[k]; q < upos[k + 1]; ++q) {
+                const int32_t j = ucol[q];
+                const int reach = lk + ulev[q] + 1;
+                if (reach > level) continue;
+                if (lev[j] == kNone) {
+                    lev[j] = reach;
+                    row.push_back(j);
+                    if (j < i) pending.push(j);
+                } else if (reach < lev[j]) {
+                    lev[j] = reach;
+                }
+            }
+        }
+        std::sort(row.begin(), row.end());
+        size_t qa = A.rp[i];
+        for (const int32_t j : row) {
+            E.ci.push_back(j);
+            // A's value where A has the entry (both lists sorted), 0 at fill
+            while (qa < (size_t)A.rp[i + 1] && A.ci[qa] < j) ++qa;
+            E.v.push_back((qa < (size_t)A.rp[i + 1] && A.ci[qa] == j) ? A.v[qa] : 0.0);
+            if (j > i) {
+                ucol.push_back(j);
+                ulev.push_back(lev[j]);
+            }
+            lev[j] = kNone;
+        }
+        E.rp[i + 1] = (int32_t)E.ci.size();
+        upos[i + 1] = (int32_t)ucol.size();
+    }
+    host_ilu0(E, L, U);
 }
 
 }  // namespace sait

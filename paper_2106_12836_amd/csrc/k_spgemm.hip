@@ -4,14 +4,17 @@
 //   split:   T~ = I - D^-1 T   (strictly triangular: its diagonal is not
 //            stored), dinv_i = fl(1/d_i), T~_ij = -(dinv_i * T_ij)
 //   passes:  M <- drop(T~ M + I), m times (Horner / Qin Jiushao form),
+//            or M <- drop(M T~ + I) (right-multiplied: used for the upper
+//            factor, so that a symmetric A gives M_U = M_L^T D^-1),
 //            drop = keep |W_ij| > tau (Alg. 2), or keep pattern S (Alg. 3),
 //            optional cap: diagonal + (cap-1) largest |W_ij| per row
 //   scale:   M <- M D^-1 (column j times dinv_j), then cast to the storage
 //            precision (FP64, binary32 RNE, bfloat16 RNE of the binary32).
 //
-// One Horner pass is a row-wise SpGEMM.  Row i of W gathers the candidate
-// products T~_il * M_lj for every l in row i of T~ (l ascending) plus the
-// unit diagonal; candidates are keyed (column j, position) and sorted by a
+// One Horner pass is a row-wise SpGEMM W = X Y + I with (X, Y) = (T~, M),
+// or (M, T~) for the right-multiplied recursion.  Row i of W gathers the
+// candidate products X_il * Y_lj for every l in row i of X (l ascending)
+// plus the unit diagonal; candidates are keyed (column j, position) and sorted by a
 // bitonic network in LDS, equal columns are then summed in key order --
 // i.e. in increasing l, the order of a Gustavson accumulator -- with
 // explicitly rounded multiply and add.  The drop rule, the cap and the
@@ -81,7 +84,9 @@ __global__ void k_split(int n, const int *__restrict__ rp, const int *__restrict
     }
 }
 
-// Candidate count of row i of T~ M + I: 1 + sum over l in T~_i of |M_l|.
+// Size of row i of X Y + I: its candidate count 1 + sum over l in X_i of
+// |Y_l|, but at least |X_i| + 1, the length of the row's segment table (a
+// row of Y may be empty: T~ has no entries in the last row of U).
 __global__ void k_count(int n, const int *__restrict__ trp, const int *__restrict__ tci,
                         const int *__restrict__ mrp, int64_t *__restrict__ cnt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -91,7 +96,8 @@ __global__ void k_count(int n, const int *__restrict__ trp, const int *__restric
         const int l = tci[p];
         c += mrp[l + 1] - mrp[l];
     }
-    cnt[i] = c;
+    const int64_t seg = (int64_t)(trp[i + 1] - trp[i]) + 1;
+    cnt[i] = c > seg ? c : seg;
 }
 
 // Tier of a row by candidate count.
@@ -189,13 +195,14 @@ __global__ void k_scan_final(const int64_t *__restrict__ in, int64_t n, const in
 }
 
 // ---------------------------------------------------------------------------
-// One row of W = T~ M + I with drop / cap / compaction.
-// key/val/kf/seg point at LDS (tiers 0-2) or at global scratch (tier 3).
+// One row of W = X Y + I with drop / cap / compaction.
+// key/val/kf/seg point at LDS (tiers 0-2) or at global scratch (tier 3),
+// sized by the row's bound from k_count.
 // ---------------------------------------------------------------------------
 struct PassArgs {
-    const int *trp, *tci;
+    const int *trp, *tci;   // X
     const double *tv;
-    const int *mrp, *mci;
+    const int *mrp, *mci;   // Y
     const double *mv;
     double tau;
     int cap;
@@ -234,12 +241,19 @@ __device__ __forceinline__ bool in_pattern(const int *sci, int b, int e, int col
     return false;
 }
 
+__device__ __forceinline__ int next_pow2(int c) {
+    int p = 1;
+    while (p < c) p <<= 1;
+    return p;
+}
+
 template <int NT>
-__device__ void pass_row(const PassArgs &a, int i, int C, int P, unsigned long long *key, double *val,
-                         unsigned char *kf, int *seg, int *shi) {
+__device__ void pass_row(const PassArgs &a, int i, unsigned long long *key, double *val, unsigned char *kf,
+                         int *seg, int *shi) {
     const int tid = threadIdx.x;
     const int tb = a.trp[i];
     const int S = a.trp[i + 1] - tb;
+    int C;  // candidates: the products plus the identity
     // 1. segment lengths -> exclusive offsets (seg[0..S], seg[S] = C-1)
     {
         const int E = (S + NT - 1) / NT;
@@ -251,7 +265,9 @@ __device__ void pass_row(const PassArgs &a, int i, int C, int P, unsigned long l
             seg[s] = len;
             local += len;
         }
-        int ex = block_scan_excl_i32<NT>(local, shi, nullptr);
+        int products;
+        int ex = block_scan_excl_i32<NT>(local, shi, &products);
+        C = products + 1;
         for (int s = s0; s < s0 + E && s < S; ++s) {
             const int len = seg[s];
             seg[s] = ex;
@@ -260,6 +276,7 @@ __device__ void pass_row(const PassArgs &a, int i, int C, int P, unsigned long l
         if (tid == 0) seg[S] = C - 1;
         __syncthreads();
     }
+    const int P = next_pow2(C);
     // 2. candidates: key = (column << 32) | candidate index; val[index] = product
     for (int c = tid; c < C - 1; c += NT) {
         int lo = 0, hi = S;  // largest s with seg[s] <= c
@@ -375,12 +392,6 @@ __device__ void pass_row(const PassArgs &a, int i, int C, int P, unsigned long l
     if (tid == 0) a.nk[i] = total;
 }
 
-__device__ __forceinline__ int next_pow2(int c) {
-    int p = 1;
-    while (p < c) p <<= 1;
-    return p;
-}
-
 template <int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_pass_lds(PassArgs a, const int *__restrict__ rows, const int64_t *__restrict__ cnt) {
     __shared__ unsigned long long key[CAP];
@@ -388,9 +399,8 @@ __global__ __launch_bounds__(NT) void k_pass_lds(PassArgs a, const int *__restri
     __shared__ unsigned char kf[CAP];
     __shared__ int seg[CAP + 1];
     __shared__ int shi[NT];
-    const int i = rows[blockIdx.x];
-    const int C = (int)cnt[i];
-    pass_row<NT>(a, i, C, next_pow2(C), key, val, kf, seg, shi);
+    (void)cnt;
+    pass_row<NT>(a, rows[blockIdx.x], key, val, kf, seg, shi);
 }
 
 template <int NT>
@@ -400,14 +410,14 @@ __global__ __launch_bounds__(NT) void k_pass_global(PassArgs a, const int *__res
     __shared__ int shi[NT];
     const int r = blockIdx.x;
     const int i = rows[r];
-    const int C = (int)cnt[i];
+    const int C = (int)cnt[i];  // the row's bound: the layout the host sized
     const int P = next_pow2(C);
     unsigned char *base = scratch + soff[r];
     unsigned long long *key = reinterpret_cast<unsigned long long *>(base);
     double *val = reinterpret_cast<double *>(base + (size_t)P * 8);
     int *seg = reinterpret_cast<int *>(base + (size_t)P * 16);
     unsigned char *kf = base + (size_t)P * 16 + (size_t)(C + 1) * 4;
-    pass_row<NT>(a, i, C, P, key, val, kf, seg, shi);
+    pass_row<NT>(a, i, key, val, kf, seg, shi);
 }
 
 // Identity M_0 = I.
@@ -617,15 +627,21 @@ void do_split(Allocator *a, const DevCsr &T, Split &sp, hipStream_t s) {
     if (herr) fail(SAIT_E_ZERO_PIVOT, "SAIT: triangular factor has a zero, missing or non-finite diagonal entry");
 }
 
-// One pass: Mnext = drop(T~ Mprev + I); if dinv != nullptr the result is
-// also scaled by D^-1 (final pass).
-void one_pass(Allocator *a, int n, const Split &sp, const DevCsr &Mprev, double tau, int cap, const int *srp,
-              const int *sci, const double *final_dinv, DevCsr &Mnext, hipStream_t s) {
+// One pass: Mnext = drop(T~ Mprev + I), or drop(Mprev T~ + I) if right; if
+// dinv != nullptr the result is also scaled by D^-1 (final pass).
+void one_pass(Allocator *a, int n, const Split &sp, const DevCsr &Mprev, bool right, double tau, int cap,
+              const int *srp, const int *sci, const double *final_dinv, DevCsr &Mnext, hipStream_t s) {
     DevBuf cnt, cptr, lists, tier_n, nk, nk64, rp64;
     cnt.alloc(a, (size_t)std::max(n, 1) * sizeof(int64_t));
     cptr.alloc(a, (size_t)(n + 1) * sizeof(int64_t));
-    hipLaunchKernelGGL(k_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, sp.trp.as<int>(), sp.tci.as<int>(),
-                       Mprev.rp.as<int>(), cnt.as<int64_t>());
+    // operands of W = X Y + I
+    const int *xrp = right ? Mprev.rp.as<int>() : sp.trp.as<int>();
+    const int *xci = right ? Mprev.ci.as<int>() : sp.tci.as<int>();
+    const double *xv = right ? Mprev.v.as<double>() : sp.tv.as<double>();
+    const int *yrp = right ? sp.trp.as<int>() : Mprev.rp.as<int>();
+    const int *yci = right ? sp.tci.as<int>() : Mprev.ci.as<int>();
+    const double *yv = right ? sp.tv.as<double>() : Mprev.v.as<double>();
+    hipLaunchKernelGGL(k_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, xrp, xci, yrp, cnt.as<int64_t>());
     SAIT_LAUNCH_CHECK();
     scan_exclusive_i64(a, cnt.as<int64_t>(), cptr.as<int64_t>(), n, s);
     int64_t total = 0;
@@ -646,12 +662,12 @@ void one_pass(Allocator *a, int n, const Split &sp, const DevCsr &Mprev, double 
     nk.alloc(a, (size_t)std::max(n, 1) * sizeof(int));
 
     PassArgs pa;
-    pa.trp = sp.trp.as<int>();
-    pa.tci = sp.tci.as<int>();
-    pa.tv = sp.tv.as<double>();
-    pa.mrp = Mprev.rp.as<int>();
-    pa.mci = Mprev.ci.as<int>();
-    pa.mv = Mprev.v.as<double>();
+    pa.trp = xrp;
+    pa.tci = xci;
+    pa.tv = xv;
+    pa.mrp = yrp;
+    pa.mci = yci;
+    pa.mv = yv;
     pa.tau = tau;
     pa.cap = cap;
     pa.srp = srp;
@@ -754,7 +770,7 @@ void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCs
     for (int k = 0; k < p_unrestricted; ++k, ++done) {
         DevCsr nxt;
         const bool last = done + 1 == total;
-        one_pass(a, n, sp, cur, 0.0, 0, nullptr, nullptr, last ? sp.dinv.as<double>() : nullptr, nxt, s);
+        one_pass(a, n, sp, cur, p.right, 0.0, 0, nullptr, nullptr, last ? sp.dinv.as<double>() : nullptr, nxt, s);
         cur = std::move(nxt);
     }
     const int *S_rp = nullptr, *S_ci = nullptr;
@@ -778,7 +794,7 @@ void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCs
     for (int k = 0; k < p.m; ++k, ++done) {
         DevCsr nxt;
         const bool last = done + 1 == total;
-        one_pass(a, n, sp, cur, p.tau, p.pattern_p >= 0 ? 0 : p.cap, S_rp, S_ci,
+        one_pass(a, n, sp, cur, p.right, p.tau, p.pattern_p >= 0 ? 0 : p.cap, S_rp, S_ci,
                  last ? sp.dinv.as<double>() : nullptr, nxt, s);
         cur = std::move(nxt);
     }
@@ -793,13 +809,13 @@ void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCs
     M = std::move(cur);
 }
 
-void sait_single_pass(Allocator *a, const DevCsr &T, const DevCsr &Mprev, double tau, int cap, DevCsr &Mnext,
-                      hipStream_t s) {
+void sait_single_pass(Allocator *a, const DevCsr &T, const DevCsr &Mprev, bool right, double tau, int cap,
+                      DevCsr &Mnext, hipStream_t s) {
     if (!(tau >= 0.0 && tau < 1.0)) fail(SAIT_E_INVALID, "SAIT: tau must satisfy 0 <= tau < 1");
     if (cap < 0) fail(SAIT_E_INVALID, "SAIT: max_nnz_row must be >= 0");
     Split sp;
     do_split(a, T, sp, s);
-    one_pass(a, (int)T.n, sp, Mprev, tau, cap, nullptr, nullptr, nullptr, Mnext, s);
+    one_pass(a, (int)T.n, sp, Mprev, right, tau, cap, nullptr, nullptr, nullptr, Mnext, s);
 }
 
 void transpose_csr(Allocator *a, const DevCsr &M, DevCsr &Mt, hipStream_t s) {

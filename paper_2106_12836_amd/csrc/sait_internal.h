@@ -113,6 +113,7 @@ struct DevCsr {
 void validate_csr(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const char *what);
 void host_ilu0(const HostCsr &A, HostCsr &L, HostCsr &U);
 void host_ilut(const HostCsr &A, double tau, int fill, HostCsr &L, HostCsr &U);
+void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U);
 
 // ---------------------------------------------------------------------------
 // SpGEMM construction of the SAIT factors (k_spgemm.hip)
@@ -123,6 +124,7 @@ struct SaitParams {
     int cap = 0;        // 0: no per-row cap
     int pattern_p = -1; // >= 0: SAIT_Pat(p, m)
     int precision = SAIT_F64;
+    bool right = false; // passes M <- drop(M T~ + I) instead of drop(T~ M + I)
 };
 
 // Upload a host CSR.
@@ -131,8 +133,9 @@ void upload_csr(Allocator *a, const HostCsr &h, DevCsr &d, hipStream_t s);
 void download_csr(const DevCsr &d, HostCsr &h, hipStream_t s);
 // Build M ~ T^-1 for a device-resident triangular T.
 void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCsr &M, hipStream_t s);
-// One unscaled pass M_next = drop(T~ M_prev + I) (test entry point).
-void sait_single_pass(Allocator *a, const DevCsr &T, const DevCsr &Mprev, double tau, int cap,
+// One unscaled pass M_next = drop(T~ M_prev + I), or drop(M_prev T~ + I)
+// if right (test entry point).
+void sait_single_pass(Allocator *a, const DevCsr &T, const DevCsr &Mprev, bool right, double tau, int cap,
                       DevCsr &Mnext, hipStream_t s);
 // Device exclusive scan of int64 counts: out[0..n] (out[n] = total).
 void scan_exclusive_i64(Allocator *a, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

@@ -21,7 +21,9 @@ _LIB = None
 
 SAIT_OK, SAIT_NOT_CONVERGED = 0, 1
 SAIT_E_INVALID, SAIT_E_ZERO_PIVOT, SAIT_E_NONFINITE, SAIT_E_NOMEM, SAIT_E_DEVICE = -1, -2, -3, -4, -5
-SAIT_ILU0, SAIT_ILUT = 0, 1
+SAIT_ILU0, SAIT_ILUT, SAIT_ILUK = 0, 1, 2
+SAIT_SIDE_LEFT, SAIT_SIDE_RIGHT = 0, 1
+SIDES = {"left": SAIT_SIDE_LEFT, "right": SAIT_SIDE_RIGHT}
 SAIT_METHOD_GMRES, SAIT_METHOD_PCG = 0, 1
 SAIT_PREC_SAIT, SAIT_PREC_JACOBI, SAIT_PREC_EXACT, SAIT_PREC_NONE = 0, 1, 2, 3
 PREC_KINDS = {"sait": SAIT_PREC_SAIT, "jacobi": SAIT_PREC_JACOBI, "exact": SAIT_PREC_EXACT, "none": SAIT_PREC_NONE}
@@ -52,6 +54,8 @@ class sait_build_opts(C.Structure):
         ("ilu_kind", C.c_int), ("ilut_tau", C.c_double), ("ilut_fill", C.c_int),
         ("m", C.c_int), ("tau", C.c_double), ("max_nnz_row", C.c_int),
         ("pattern_p", C.c_int), ("precision", C.c_int), ("build_transpose", C.c_int),
+        ("ilu_level", C.c_int),
+        ("upper_side", C.c_int),
     ]
 
 
@@ -101,8 +105,8 @@ def lib():
         L.sait_time_apply.argtypes = [vp, vp, vp, C.c_int, vp, f64p, f64p, f64p]
         L.sait_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.sait_set_preconditioner.argtypes = [vp, C.c_int, C.c_int, vp]
-        L.sait_debug_step.argtypes = [i64, i32p, i32p, f64p, i32p, i32p, f64p, C.c_double, C.c_int, i64,
-                                      i32p, i32p, f64p, C.POINTER(C.c_int64)]
+        L.sait_debug_step.argtypes = [i64, i32p, i32p, f64p, i32p, i32p, f64p, C.c_double, C.c_int, C.c_int,
+                                      i64, i32p, i32p, f64p, C.POINTER(C.c_int64)]
         _LIB = L
     return _LIB
 
@@ -145,7 +149,9 @@ def default_build_opts(**kw) -> sait_build_opts:
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
         if k == "ilu_kind" and isinstance(v, str):
-            v = {"ilu0": SAIT_ILU0, "ilut": SAIT_ILUT}[v]
+            v = {"ilu0": SAIT_ILU0, "ilut": SAIT_ILUT, "iluk": SAIT_ILUK}[v]
+        if k == "upper_side" and isinstance(v, str):
+            v = SIDES[v]
         setattr(o, k, v)
     return o
 
@@ -283,8 +289,9 @@ def sait_copy(src, dst, stream=None):
     return _check(lib().sait_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, _stream(stream)))
 
 
-def sait_debug_step(n, T, M, tau, max_nnz_row=0):
-    """T, M: (row_ptr, col_idx, val) host arrays.  Returns the device pass as (rp, ci, v)."""
+def sait_debug_step(n, T, M, tau, max_nnz_row=0, side="left"):
+    """T, M: (row_ptr, col_idx, val) host arrays; side "left" (T~ M + I) or
+    "right" (M T~ + I).  Returns the device pass as (rp, ci, v)."""
     Trp, Tci, Tv = (np.ascontiguousarray(T[0], np.int32), np.ascontiguousarray(T[1], np.int32),
                     np.ascontiguousarray(T[2], np.float64))
     Mrp, Mci, Mv = (np.ascontiguousarray(M[0], np.int32), np.ascontiguousarray(M[1], np.int32),
@@ -296,7 +303,7 @@ def sait_debug_step(n, T, M, tau, max_nnz_row=0):
     nnz = C.c_int64()
     st = lib().sait_debug_step(int(n), _ptr(Trp, C.c_int32), _ptr(Tci, C.c_int32), _ptr(Tv, C.c_double),
                                _ptr(Mrp, C.c_int32), _ptr(Mci, C.c_int32), _ptr(Mv, C.c_double), float(tau),
-                               int(max_nnz_row), int(cap), _ptr(orp, C.c_int32), _ptr(oci, C.c_int32),
+                               int(max_nnz_row), SIDES[side], int(cap), _ptr(orp, C.c_int32), _ptr(oci, C.c_int32),
                                _ptr(ov, C.c_double), C.byref(nnz))
     _check(st)
     return orp, oci[: nnz.value].copy(), ov[: nnz.value].copy()
@@ -321,7 +328,7 @@ class SaitPreconditioner:
     A: any object with ``n``, ``rp``, ``ci``, ``v`` (e.g. workloads.Csr) or
     a scipy sparse matrix.  Keyword options mirror sait_build_opts
     (ilu_kind, ilut_tau, ilut_fill, m, tau, max_nnz_row, pattern_p,
-    precision, build_transpose).
+    precision, build_transpose, ilu_level, upper_side: "right" or "left").
     """
 
     def __init__(self, A, nsys: int = 1, sys_ptr=None, stream=None, **opts):

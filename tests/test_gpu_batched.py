@@ -28,7 +28,7 @@ def _check(A, sys_ptr, B, X, infos, tau, m, restart, rtol, nrhs):
         s0, s1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
         As = _block(A, s0, s1)
         L, U = oracle.ilu0(As)
-        ML, MU = oracle.sait_thr(L, tau, m), oracle.sait_thr(U, tau, m)
+        ML, MU = oracle.sait_factors(L, U, m, tau=tau)
         for q in range(nrhs):
             inf = infos[s * nrhs + q]
             b = B[s0:s1, q]
@@ -86,7 +86,7 @@ def test_batched_maxit_and_restart_one():
             s0, s1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
             As = _block(A, s0, s1)
             L, U = oracle.ilu0(As)
-            ML, MU = oracle.sait_thr(L, 1e-2, 3), oracle.sait_thr(U, 1e-2, 3)
+            ML, MU = oracle.sait_factors(L, U, 3, tau=1e-2)
             for q in range(2):
                 ref = oracle.gmres(As, B[s0:s1, q], ("sait64", ML, MU), restart=4, maxit=6, rtol=1e-14)
                 inf = infos[s * 2 + q]
@@ -97,7 +97,7 @@ def test_batched_maxit_and_restart_one():
             s0, s1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
             As = _block(A, s0, s1)
             L, U = oracle.ilu0(As)
-            ML, MU = oracle.sait_thr(L, 1e-2, 3), oracle.sait_thr(U, 1e-2, 3)
+            ML, MU = oracle.sait_factors(L, U, 3, tau=1e-2)
             for q in range(2):
                 ref = oracle.gmres(As, B[s0:s1, q], ("sait64", ML, MU), restart=1, maxit=300, rtol=1e-6)
                 inf = infos[s * 2 + q]
@@ -144,7 +144,7 @@ def test_batched_c4_full_size():
         s0, s1 = int(sys_ptr[s]), int(sys_ptr[s + 1])
         As = Csr.from_scipy(S[s0:s1, s0:s1])
         L, U = oracle.ilu0(As)
-        ML, MU = oracle.sait_thr(L, c["tau"], c["m"]), oracle.sait_thr(U, c["tau"], c["m"])
+        ML, MU = oracle.sait_factors(L, U, c["m"], tau=c["tau"])
         for q in range(R):
             ref = oracle.gmres(As, B[s0:s1, q], ("sait64", ML, MU), restart=c["restart"], rtol=c["rtol"])
             assert abs(infos[s * R + q].iterations - ref["iters"]) <= 1, (s, q, infos[s * R + q].iterations,

@@ -29,11 +29,16 @@ def _cmp_csr(rp, ci, v, ref: Csr, what):
     assert err.max(initial=0.0) <= RTOL, f"{what}: max rel err {err.max()}"
 
 
-def _oracle_factors(A, ilu, m, tau, cap=0, p=-1, ilut=(1e-3, 10)):
-    L, U = oracle.ilu0(A) if ilu == "ilu0" else oracle.ilut(A, *ilut)
+def _oracle_factors(A, ilu, m, tau, cap=0, p=-1, ilut=(1e-3, 10), level=1, upper_side="right"):
+    if ilu == "ilu0":
+        L, U = oracle.ilu0(A)
+    elif ilu == "iluk":
+        L, U = oracle.iluk(A, level)
+    else:
+        L, U = oracle.ilut(A, *ilut)
     if p >= 0:
-        return L, U, oracle.sait_pat(L, p, m), oracle.sait_pat(U, p, m)
-    return L, U, oracle.sait_thr(L, tau, m, cap), oracle.sait_thr(U, tau, m, cap)
+        return (L, U, *oracle.sait_factors(L, U, m, p=p, upper_side=upper_side))
+    return (L, U, *oracle.sait_factors(L, U, m, tau=tau, cap=cap, upper_side=upper_side))
 
 
 CASES = [
@@ -44,8 +49,16 @@ CASES = [
     ("rdd-ragged", lambda: random_diag_dominant(3001, 8, band=300, seed=3), dict(m=3, tau=1e-2)),
     ("rdd-wide", lambda: random_diag_dominant(2000, 8, band=None, seed=4), dict(m=2, tau=0.0)),
     ("convdiff-ilut", lambda: convdiff2d_upwind(40, 10.0), dict(m=4, tau=1e-3, ilu_kind="ilut")),
+    ("poisson3d-ilu1", lambda: poisson3d(10), dict(m=10, tau=0.02, ilu_kind="iluk", ilu_level=1)),
+    ("rdd-ilu2", lambda: random_diag_dominant(1500, 8, band=120, seed=6), dict(m=3, tau=1e-2, ilu_kind="iluk",
+                                                                                ilu_level=2)),
     ("cap5", lambda: poisson3d(7), dict(m=4, tau=0.0, max_nnz_row=5)),
+    ("rdd-cap6", lambda: random_diag_dominant(1200, 8, band=90, seed=8), dict(m=3, tau=1e-3, max_nnz_row=6)),
     ("pat2", lambda: poisson3d(8), dict(m=3, tau=0.0, pattern_p=2)),
+    ("rdd-upper-left", lambda: random_diag_dominant(2500, 8, band=200, seed=9), dict(m=3, tau=1e-2,
+                                                                                     upper_side="left")),
+    ("rdd-pat2-upper-left", lambda: random_diag_dominant(900, 6, band=60, seed=10), dict(m=3, tau=0.0, pattern_p=2,
+                                                                                         upper_side="left")),
     ("m0", lambda: poisson2d(9), dict(m=0, tau=0.1)),
     ("n1", lambda: Csr(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])), dict(m=2, tau=0.1)),
 ]
@@ -57,7 +70,8 @@ def test_factors_match_oracle(name, maker, opts):
     A = maker()
     ilu = opts.get("ilu_kind", "ilu0")
     L, U, ML, MU = _oracle_factors(A, ilu, opts["m"], opts["tau"], opts.get("max_nnz_row", 0),
-                                   opts.get("pattern_p", -1))
+                                   opts.get("pattern_p", -1), level=opts.get("ilu_level", 1),
+                                   upper_side=opts.get("upper_side", "right"))
     pre = SaitPreconditioner(A, **opts)
     try:
         for which, ref in (("L", L), ("U", U)):
@@ -94,16 +108,17 @@ def test_dense_rows_all_tiers():
     # tau = 0 with m = n-1 on a dense-ish triangular matrix: rows reach
     # thousands of candidate products (LDS tiers and the global fallback),
     # and the result must be the exact inverse (Eq. T_inverse).
-    print("[test_dense_rows_all_tiers]", flush=True)
     for lower in (True, False):
         T = random_triangular(160, 0.5, 11, lower=lower, diag_range=(2.0, 3.0))
-        # one pass at a time through the debug entry point (T itself as input)
-        Mk = oracle.identity(160)
-        for k in range(12):
-            rp, ci, v = sait_debug_step(160, (T.rp, T.ci, T.v), (Mk.rp, Mk.ci, Mk.v), 0.0)
-            ref = oracle.sait_step(T, Mk, 0.0)
-            _cmp_csr(rp, ci, v, ref, f"pass {k}")
-            Mk = ref
+        for side in ("left", "right"):
+            print(f"[test_dense_rows_all_tiers] lower={lower} side={side}", flush=True)
+            # one pass at a time through the debug entry point (T itself as input)
+            Mk = oracle.identity(160)
+            for k in range(12):
+                rp, ci, v = sait_debug_step(160, (T.rp, T.ci, T.v), (Mk.rp, Mk.ci, Mk.v), 0.0, side=side)
+                ref = oracle.sait_step(T, Mk, 0.0, side=side)
+                _cmp_csr(rp, ci, v, ref, f"pass {k}")
+                Mk = ref
         # after 159 passes the scaled series is the exact inverse
         Tinv = np.linalg.inv(T.to_scipy().toarray())
         assert np.abs(oracle.sait_thr(T, 0.0, 159).to_scipy().toarray() - Tinv).max() < 1e-10 * np.abs(Tinv).max()
@@ -142,19 +157,35 @@ def test_long_rows_apply():
         pre.close()
 
 
+@pytest.mark.parametrize("side", ["left", "right"])
 @pytest.mark.parametrize("tau,cap", [(0.0, 0), (1e-2, 0), (0.05, 0), (0.0, 4), (1e-3, 7)])
-def test_stepwise_harness(tau, cap):
+def test_stepwise_harness(tau, cap, side):
     # Each device pass is fed the oracle's previous M (never the reverse).
-    print(f"[test_stepwise_harness] tau={tau} cap={cap}", flush=True)
+    print(f"[test_stepwise_harness] tau={tau} cap={cap} side={side}", flush=True)
     A = random_diag_dominant(1500, 8, band=100, seed=21)
     L, U = oracle.ilu0(A)
     for T in (L, U):
         M = oracle.identity(A.n)
         for k in range(4):
-            rp, ci, v = sait_debug_step(A.n, (T.rp, T.ci, T.v), (M.rp, M.ci, M.v), tau, cap)
-            ref = oracle.sait_step(T, M, tau, cap)
+            rp, ci, v = sait_debug_step(A.n, (T.rp, T.ci, T.v), (M.rp, M.ci, M.v), tau, cap, side=side)
+            ref = oracle.sait_step(T, M, tau, cap, side=side)
             _cmp_csr(rp, ci, v, ref, f"pass {k}")
             M = ref
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_empty_operand_rows(side):
+    # T diagonal (T~ = 0): in M T~ + I every product segment of a row of M is
+    # empty, so a row has far more segments than candidates (rows of M up to
+    # 2600 entries reach every size tier); the result is the identity.
+    print(f"[test_empty_operand_rows] side={side}", flush=True)
+    n = 2600
+    T = Csr(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.linspace(1.0, 2.0, n))
+    M = Csr.from_scipy(sp.csr_matrix(np.tril(np.random.default_rng(3).uniform(0.5, 1.0, (n, n)))))
+    rp, ci, v = sait_debug_step(n, (T.rp, T.ci, T.v), (M.rp, M.ci, M.v), 0.0, side=side)
+    ref = oracle.sait_step(T, M, 0.0, side=side)
+    assert ref.nnz == n
+    _cmp_csr(rp, ci, v, ref, side)
 
 
 def test_build_errors():
@@ -165,6 +196,9 @@ def test_build_errors():
     assert e.value.status == -2  # zero pivot
     with pytest.raises(SaitError) as e:
         SaitPreconditioner(poisson2d(4), tau=1.0)
+    assert e.value.status == -1
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(poisson2d(4), upper_side=2)
     assert e.value.status == -1
     bad = Csr(2, np.array([0, 2, 3], np.int32), np.array([1, 0, 1], np.int32), np.array([1.0, 1.0, 1.0]))
     with pytest.raises(SaitError) as e:

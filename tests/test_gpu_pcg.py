@@ -67,7 +67,7 @@ def test_exact_apply_bit_exact(name, make):
 
 def _oracle_prec(kind, L, U, sweeps=3, tau=1e-2, m=3):
     if kind == "sait":
-        return ("sait64", oracle.sait_thr(L, tau, m), oracle.sait_thr(U, tau, m))
+        return ("sait64", *oracle.sait_factors(L, U, m, tau=tau))
     if kind == "jacobi":
         return ("jacobi", L, U, sweeps)
     if kind == "exact":
@@ -140,7 +140,7 @@ def test_pcg_paper_experiment(paper_problem, kind):
     print(f"[test_pcg_paper_experiment] {kind}", flush=True)
     A, L, U, f, printed = paper_problem
     if kind == "sait":
-        ref = oracle.pcg(A, f, ("sait64", oracle.sait_thr(L, 0.05, 10), oracle.sait_thr(U, 0.05, 10)), rtol=1e-10)
+        ref = oracle.pcg(A, f, ("sait64", *oracle.sait_factors(L, U, 10, tau=0.05)), rtol=1e-10)
         want = {t: it for t, m, it in printed["sait_thr"]}[0.05]
     else:
         ref = oracle.pcg(A, f, ("jacobi", L, U, 3), rtol=1e-10)

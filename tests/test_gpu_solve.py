@@ -35,7 +35,7 @@ def _sp(M: Csr, vals=None):
 
 def _factors(A, tau, m, ilu="ilu0"):
     L, U = oracle.ilu0(A) if ilu == "ilu0" else oracle.ilut(A, 1e-3, 10)
-    return L, U, oracle.sait_thr(L, tau, m), oracle.sait_thr(U, tau, m)
+    return (L, U, *oracle.sait_factors(L, U, m, tau=tau))
 
 
 APPLY_CASES = [
