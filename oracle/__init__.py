@@ -387,3 +387,7 @@ def gmres(A: Csr, b, prec=None, x0=None, restart=30, maxit=10000, rtol=1e-8, fle
     if history:
         out["hist"] = hist[: it.value]
     return out
+
+
+from . import lobpcg as lobpcg_module  # noqa: E402  (LOBPCG of the eigenvalue experiment, Sec. 4)
+from .lobpcg import lobpcg  # noqa: E402,F401
