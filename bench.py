@@ -15,9 +15,13 @@ wall time, systems/s, pair-iterations/s and the modelled bytes per second
 diagonally dominant matrices and on the 2D convection-diffusion factors
 (also after a cache-evicting write), and the forward / adjoint solve times
 of the differentiable 512^2 workload.  `paper_experiment`: the paper's
-PCG experiment (3D Laplace 100^3, level-0 ILU, 1e-10) with the SAIT
-preconditioners of its tables, 1..15 Jacobi sweeps, the exact triangular
-solves and no preconditioner: iterations and seconds per solve.
+PCG experiment (3D Laplace 100^3, level-0 and level-1 ILU, 1e-10) with the
+SAIT preconditioners of its tables, 1..15 Jacobi sweeps, the exact
+triangular solves and no preconditioner: iterations and seconds per solve.
+`eigen_experiment`: the paper's LOBPCG experiment (the 4 smallest
+eigenpairs of the same matrix, SAIT_Thr(0.01, 10) block preconditioning,
+beside the exact solves and none): steps, seconds, error against the
+closed-form spectrum.
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -368,6 +372,58 @@ def paper_experiment(torch, dev):
     return out
 
 
+def eigen_experiment(torch, dev, levels=(0, 1)):
+    """The paper's eigenvalue experiment (Sec. 4): the 4 smallest eigenpairs
+    of the 7-point Laplacian on the 100^3 interior by LOBPCG, preconditioned
+    by SAIT_Thr(0.01, 10) of the level-0 / level-1 ILU factors (the residual
+    block through two sparse matrix-matrix products per step), beside the
+    exact triangular solves and no preconditioner; tolerance 1e-8 relative
+    per eigenpair; start block U[-1, 1] (seed 0).  Wall time per solve (the
+    build reported apart), steps, and the error of the Ritz values against
+    the closed-form spectrum."""
+    from paper_2106_12836_amd import SaitPreconditioner
+    from workloads import poisson3d
+
+    s = 100
+    A = poisson3d(s)
+    t = np.sin(np.arange(1, 5) * np.pi / (2 * (s + 1))) ** 2
+    exact = np.sort([4 * (t[i] + t[j] + t[l]) for i in range(4) for j in range(4) for l in range(4)])[:4]
+    X0 = torch.tensor(np.random.default_rng(0).uniform(-1.0, 1.0, (A.n, 4)), device=dev)
+
+    def timed(pre, maxit):
+        pre.lobpcg(X0, tol=1e-8, maxit=2)  # warm-up: allocates the blocks
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, X, info = pre.lobpcg(X0, tol=1e-8, maxit=maxit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dict(iterations=info["iterations"], status=info["status"], p_drops=info["p_drops"],
+                    relres=info["relres"], seconds=round(dt, 4),
+                    ms_per_step=round(1e3 * dt / max(info["iterations"], 1), 4),
+                    max_rel_err_vs_closed_form=float(np.max(np.abs(lam - exact) / exact)))
+
+    out = dict(workload="3D 7-point Laplace 100^3 (n = 10^6), LOBPCG, 4 smallest eigenpairs, tol 1e-8, "
+                        "X0 ~ U[-1,1] (seed 0)", eigenvalues_closed_form=[float(x) for x in exact])
+    for level in levels:
+        opts = dict(m=10, tau=0.01)
+        if level:
+            opts.update(ilu_kind="iluk", ilu_level=1)
+        t0 = time.time()
+        pre = SaitPreconditioner(A, **opts)
+        torch.cuda.synchronize()
+        rec = dict(build_s=round(time.time() - t0, 3), ratio_L=round(pre.query()["ratio_L"], 4))
+        rec["sait"] = timed(pre, 3000)
+        pre.set_preconditioner("exact")
+        rec["exact"] = timed(pre, 3000)
+        if level == 0:
+            pre.set_preconditioner("none")
+            out["none"] = timed(pre, 5000)
+        pre.close()
+        out[f"level{level}"] = rec
+        print(f"[bench] eigen experiment, level-{level} ILU: {rec}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,6 +436,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 256-system solve")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (rdd, c2, c5)")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's PCG experiment (100^3)")
+    ap.add_argument("--no-eigen", action="store_true", help="skip the paper's LOBPCG experiment (100^3)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched solve and print its record (for profiling that launch)")
     args = ap.parse_args()
@@ -500,6 +557,9 @@ def main():
     paper = None
     if not args.no_paper:
         paper = paper_experiment(torch, dev)
+    eigen = None
+    if not args.no_eigen:
+        eigen = eigen_experiment(torch, dev)
 
     batched = None
     if not args.no_batched:
@@ -539,6 +599,7 @@ def main():
         "batched": batched,
         "other_workloads": extra,
         "paper_experiment": paper,
+        "eigen_experiment": eigen,
     }
     print(json.dumps(line), flush=True)
 

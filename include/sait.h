@@ -46,6 +46,7 @@ typedef struct sait_handle_s *sait_handle;
 enum {
     SAIT_OK = 0,
     SAIT_NOT_CONVERGED = 1,   /* solve hit maxit; x holds the last iterate */
+    SAIT_BREAKDOWN = 2,       /* LOBPCG: the trial basis became numerically dependent */
     SAIT_E_INVALID = -1,      /* bad argument, malformed CSR, unsupported shape */
     SAIT_E_ZERO_PIVOT = -2,   /* zero (or missing) diagonal in ILU or in a SAIT input */
     SAIT_E_NONFINITE = -3,    /* NaN/Inf in an input or produced by a factorisation */
@@ -279,6 +280,45 @@ int sait_time_apply(sait_handle h, const double *r, double *z, int reps, void *h
  * SpMV rates are compared with.
  */
 int sait_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
+/* LOBPCG options (sait_default_eig_opts fills the defaults in brackets). */
+typedef struct {
+    int maxit;           /* maximum steps [1000] */
+    double tol;          /* stop when every ||A x_j - theta_j x_j||_2 <= tol |theta_j| (||x_j|| = 1) [1e-8] */
+} sait_eig_opts;
+
+/* LOBPCG report. */
+typedef struct {
+    int iterations;      /* Rayleigh-Ritz steps after the one on span(X0) */
+    int status;          /* SAIT_OK, SAIT_NOT_CONVERGED or SAIT_BREAKDOWN */
+    int p_drops;         /* steps whose Rayleigh-Ritz ran on [X, W] (basis [X, W, P] numerically dependent) */
+    double relres;       /* max_j ||A x_j - theta_j x_j|| / |theta_j| at exit */
+} sait_eig_info;
+
+void sait_default_eig_opts(sait_eig_opts *o);
+
+/*
+ * The k smallest eigenpairs of a symmetric positive definite A by LOBPCG
+ * (Knyazev's locally optimal block preconditioned conjugate gradient), the
+ * eigensolver of the eigenvalue experiment in Sec. 4.  Every step applies
+ * the handle's preconditioner (sait_set_preconditioner; SAIT: W = M_U (M_L R)
+ * for the whole n x k residual block, two sparse matrix-matrix products) and
+ * A W, forms the Gram matrices of the trial basis [X, W, P] on the device
+ * and solves its Rayleigh-Ritz problem (order <= 3k) on the host: if the
+ * unit-diagonal scaled S^T S has a Cholesky pivot <= 1e-14 that step drops
+ * P, and if [X, W] fails too the solve stops with SAIT_BREAKDOWN.
+ * A must be symmetric and the preconditioner symmetric positive definite
+ * (SAIT with upper_side = SAIT_SIDE_RIGHT on a symmetric A is); neither is
+ * checked.  Single-system handles only.
+ * X: device, n x k row-major (ld = k), 1 <= k <= 5, n >= 3k: the start block
+ *    (full column rank) on entry, the Ritz vectors (orthonormal) on exit.
+ * lambda: host, k Ritz values, ascending.  history: host, maxit + 1 entries
+ * or NULL: the residual maximum before every step.  info may be NULL.
+ * Returns SAIT_OK, SAIT_NOT_CONVERGED (maxit), SAIT_BREAKDOWN, or an error
+ * (SAIT_E_INVALID: bad k, n < 3k, nsys > 1, rank-deficient start block).
+ */
+int sait_lobpcg(sait_handle h, double *X, int k, double *lambda, double *history, const sait_eig_opts *o,
+                sait_eig_info *info, void *hip_stream);
 
 /*
  * Test entry point: one unscaled Horner pass on the device,

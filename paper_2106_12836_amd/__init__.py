@@ -12,6 +12,7 @@ from .sait import (  # noqa: F401
     SaitPreconditioner,
     SolveResult,
     default_build_opts,
+    default_eig_opts,
     default_solve_opts,
     lib,
     library_path,
@@ -28,6 +29,7 @@ from .sait import (  # noqa: F401
     sait_matvec,
     sait_query,
     sait_set_apply_lanes,
+    sait_lobpcg,
     sait_set_preconditioner,
     sait_set_values,
     sait_solve,

@@ -6,6 +6,7 @@
 #include <memory>
 #include <string>
 
+#include "lobpcg.h"
 #include "sait_internal.h"
 #include "solver.h"
 
@@ -78,6 +79,8 @@ struct sait_handle_s {
     DevBuf At_perm; // At.v[q] = A.v[At_perm[q]]
     Solver solver;
     BatchedSolver batched;
+    Lobpcg lobpcg;
+    DevBuf col1, col2;  // one column of a block (block LOBPCG with a one-vector preconditioner)
     // preconditioner selected by sait_set_preconditioner (built on first use)
     int prec_kind = SAIT_PREC_SAIT;
     int sweeps = 1;
@@ -387,6 +390,44 @@ int sait_solve(sait_handle h, const double *b, double *x, int nrhs, int64_t ld, 
             return status;
         }
         return h->solver.solve(&h->alloc, solve_ops(h, transpose), b, x, opts, info, as_stream(hip_stream));
+    });
+}
+
+void sait_default_eig_opts(sait_eig_opts *o) {
+    if (!o) return;
+    o->maxit = 1000;
+    o->tol = 1e-8;
+}
+
+int sait_lobpcg(sait_handle h, double *X, int k, double *lambda, double *history, const sait_eig_opts *o,
+                sait_eig_info *info, void *hip_stream) {
+    return guard([&]() -> int {
+        check_handle(h);
+        if (h->nsys != 1) fail(SAIT_E_INVALID, "LOBPCG runs on single-system handles");
+        sait_eig_opts opts;
+        sait_default_eig_opts(&opts);
+        if (o) opts = *o;
+        hipStream_t s = as_stream(hip_stream);
+        const int64_t n = h->n;
+        BlockOp applyA = [h, k](const double *x, double *y, hipStream_t st) {
+            spmv(h->A, x, XKind::F64, y, YKind::F64, k, k, k, h->lanesA, st);
+        };
+        BlockOp applyT = [h, k, n](const double *r, double *w, hipStream_t st) {
+            if (h->prec_kind == SAIT_PREC_SAIT) {
+                apply_impl(h, r, w, k, k, 0, st);
+                return;
+            }
+            // the Jacobi, exact and identity preconditioners take one vector
+            const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(double);
+            if (h->col1.bytes() < bytes) h->col1.alloc(&h->alloc, bytes);
+            if (h->col2.bytes() < bytes) h->col2.alloc(&h->alloc, bytes);
+            for (int j = 0; j < k; ++j) {
+                copy_strided(r + j, k, h->col1.as<double>(), 1, n, st);
+                apply_impl(h, h->col1.as<double>(), h->col2.as<double>(), 1, 1, 0, st);
+                copy_strided(h->col2.as<double>(), 1, w + j, k, n, st);
+            }
+        };
+        return h->lobpcg.run(&h->alloc, n, k, X, applyA, applyT, opts, lambda, history, info, s);
     });
 }
 

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsait.so")
 _LIB = None
 
-SAIT_OK, SAIT_NOT_CONVERGED = 0, 1
+SAIT_OK, SAIT_NOT_CONVERGED, SAIT_BREAKDOWN = 0, 1, 2
 SAIT_E_INVALID, SAIT_E_ZERO_PIVOT, SAIT_E_NONFINITE, SAIT_E_NOMEM, SAIT_E_DEVICE = -1, -2, -3, -4, -5
 SAIT_ILU0, SAIT_ILUT, SAIT_ILUK = 0, 1, 2
 SAIT_SIDE_LEFT, SAIT_SIDE_RIGHT = 0, 1
@@ -35,7 +35,7 @@ EXPORTED = (
     "sait_default_build_opts", "sait_default_solve_opts", "sait_build", "sait_apply", "sait_matvec",
     "sait_solve", "sait_set_values", "sait_grad_values", "sait_query", "sait_export", "sait_destroy", "sait_last_error",
     "sait_autotune", "sait_set_apply_lanes", "sait_get_apply_lanes", "sait_time_apply", "sait_debug_step", "sait_copy",
-    "sait_set_preconditioner",
+    "sait_set_preconditioner", "sait_default_eig_opts", "sait_lobpcg",
 )
 
 
@@ -69,6 +69,14 @@ class sait_solve_info(C.Structure):
                 ("est_relres", C.c_double), ("true_relres", C.c_double)]
 
 
+class sait_eig_opts(C.Structure):
+    _fields_ = [("maxit", C.c_int), ("tol", C.c_double)]
+
+
+class sait_eig_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("status", C.c_int), ("p_drops", C.c_int), ("relres", C.c_double)]
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -86,6 +94,9 @@ def lib():
         L.sait_default_build_opts.restype = None
         L.sait_default_solve_opts.argtypes = [C.POINTER(sait_solve_opts)]
         L.sait_default_solve_opts.restype = None
+        L.sait_default_eig_opts.argtypes = [C.POINTER(sait_eig_opts)]
+        L.sait_default_eig_opts.restype = None
+        L.sait_lobpcg.argtypes = [vp, vp, C.c_int, f64p, f64p, C.POINTER(sait_eig_opts), C.POINTER(sait_eig_info), vp]
         L.sait_build.argtypes = [i64, i32p, i32p, f64p, C.c_int, C.POINTER(C.c_int64),
                                  C.POINTER(sait_build_opts), C.POINTER(sait_allocator), vp, C.POINTER(vp)]
         L.sait_apply.argtypes = [vp, vp, vp, C.c_int, i64, C.c_int, vp]
@@ -201,6 +212,28 @@ def sait_solve(h, b, x, nrhs=1, ld=None, transpose=0, opts=None, ninfo=1, stream
     out = [dict(iterations=i.iterations, restarts=i.restarts, status=i.status, est_relres=i.est_relres,
                 true_relres=i.true_relres) for i in infos]
     return st, out
+
+
+def default_eig_opts(**kw) -> sait_eig_opts:
+    o = sait_eig_opts()
+    lib().sait_default_eig_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def sait_lobpcg(h, X, k, opts=None, history=False, stream=None):
+    """X: device n x k row-major block (start block in, Ritz vectors out).
+    Returns (status, lambda (k,), info dict, history array or None)."""
+    lam = np.zeros(int(k))
+    o = opts if opts is not None else default_eig_opts()
+    hist = np.zeros(o.maxit + 1) if history else None
+    info = sait_eig_info()
+    st = lib().sait_lobpcg(h, _dptr(X), int(k), _ptr(lam, C.c_double), _ptr(hist, C.c_double) if history else None,
+                           C.byref(o), C.byref(info), _stream(stream))
+    _check(st)
+    out = dict(iterations=info.iterations, status=info.status, p_drops=info.p_drops, relres=info.relres)
+    return st, lam, out, (hist[: info.iterations + 1] if history else None)
 
 
 def sait_set_values(h, vals, stream=None):
@@ -403,6 +436,15 @@ class SaitPreconditioner:
                                method={"gmres": SAIT_METHOD_GMRES, "pcg": SAIT_METHOD_PCG}[method])
         st, infos = sait_solve(self.handle, b, x, nrhs, nrhs, int(transpose), o, self.nsys * nrhs, stream)
         return x, [SolveResult(**i) for i in infos]
+
+    def lobpcg(self, X0, tol=1e-8, maxit=1000, history=False, stream=None):
+        """The k = X0.shape[1] smallest eigenpairs by LOBPCG with the current
+        preconditioner.  X0: (n, k) float64 device tensor (copied).  Returns
+        (lambda (numpy), X (tensor), info dict[, history])."""
+        X = X0.contiguous().clone()
+        st, lam, info, hist = sait_lobpcg(self.handle, X, X.shape[1], default_eig_opts(maxit=maxit, tol=tol),
+                                          history, stream)
+        return (lam, X, info, hist) if history else (lam, X, info)
 
     def export(self, which: str):
         idx = {"A": SAIT_MAT_A, "L": SAIT_MAT_L, "U": SAIT_MAT_U, "ML": SAIT_MAT_ML, "MU": SAIT_MAT_MU}[which]
