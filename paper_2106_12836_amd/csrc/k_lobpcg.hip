@@ -51,11 +51,15 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(GramArgs a, double *__res
     const double *S = on ? a.s[b] : nullptr;
     const double *AS = on ? a.as[b] : nullptr;
     v4d ga0 = {0, 0, 0, 0}, gb0 = {0, 0, 0, 0}, ga1 = {0, 0, 0, 0}, gb1 = {0, 0, 0, 0};
-    const int64_t stride = (int64_t)gridDim.x * (kGramThreads / 64);
-    int64_t q = (int64_t)blockIdx.x * (kGramThreads / 64) + wave;
+    // every wavefront takes a contiguous range of quads (whole cache lines),
     // two quads per iteration into alternating accumulators
-    for (; q + stride < a.quads; q += 2 * stride) {
-        const int64_t r0 = q * 4 + kk, r1 = (q + stride) * 4 + kk;
+    const int64_t waves = (int64_t)gridDim.x * (kGramThreads / 64);
+    const int64_t chunk = (a.quads + waves - 1) / waves;
+    const int64_t q0 = ((int64_t)blockIdx.x * (kGramThreads / 64) + wave) * chunk;
+    const int64_t q1 = q0 + chunk < a.quads ? q0 + chunk : a.quads;
+    int64_t q = q0;
+    for (; q + 1 < q1; q += 2) {
+        const int64_t r0 = q * 4 + kk, r1 = r0 + 4;
         double s0 = 0.0, t0 = 0.0, s1 = 0.0, t1 = 0.0;
         if (on) {
             if (r0 < a.n) {
@@ -72,7 +76,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(GramArgs a, double *__res
         ga1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1, t1, ga1, 0, 0, 0);
         gb1 = __builtin_amdgcn_mfma_f64_16x16x4f64(s1, s1, gb1, 0, 0, 0);
     }
-    if (q < a.quads) {
+    if (q < q1) {
         const int64_t r0 = q * 4 + kk;
         double s0 = 0.0, t0 = 0.0;
         if (on && r0 < a.n) {
@@ -116,37 +120,70 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 }
 
 struct UpdArgs {
-    double *x, *ax, *w, *aw, *p, *ap, *r;  // n x K row-major blocks
-    const double *coef;                     // (nb K) x K, row-major
+    double *x, *ax, *w, *aw, *p, *ap, *r;  // n x K row-major blocks, 16-byte aligned
+    const double *coef;                     // (NB K) x K, row-major
     const double *theta;                    // K Ritz values
     int64_t n;
-    int nb;                                 // blocks in the basis (1: [X], 2: [X, W], 3: [X, W, P])
 };
 
-// X <- S c, A X <- (A S) c, P <- [W, P] c_(W,P), A P likewise (nb >= 2),
-// R = A X - X diag(theta); per-workgroup partial sums of R_j^2.
-template <int K>
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// One row of a block: 16-byte accesses when K is even.
+template <int K> __device__ __forceinline__ void load_row(const double *p, double (&o)[K]) {
+    if constexpr (K % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            const d2v v = *reinterpret_cast<const d2v *>(p + 2 * i);
+            o[2 * i] = v.x;
+            o[2 * i + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) o[i] = p[i];
+    }
+}
+template <int K> __device__ __forceinline__ void store_row(double *p, const double (&o)[K]) {
+    if constexpr (K % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) {
+            d2v v;
+            v.x = o[2 * i];
+            v.y = o[2 * i + 1];
+            *reinterpret_cast<d2v *>(p + 2 * i) = v;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) p[i] = o[i];
+    }
+}
+
+// X <- S c, A X <- (A S) c, P <- [W, P] c_(W,P), A P likewise (NB >= 2),
+// R = A X - X diag(theta); per-workgroup partial sums of R_j^2 (wavefront
+// shuffles, then the four wavefronts in a fixed order).
+template <int K, int NB>
 __global__ __launch_bounds__(kUpdThreads) void k_lob_update(UpdArgs a, double *__restrict__ part) {
     const int64_t row = (int64_t)blockIdx.x * kUpdThreads + threadIdx.x;
     double r2[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) r2[j] = 0.0;
     if (row < a.n) {
-        double s[3][K], t[3][K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            s[0][j] = a.x[row * K + j];
-            t[0][j] = a.ax[row * K + j];
-            s[1][j] = a.nb > 1 ? a.w[row * K + j] : 0.0;
-            t[1][j] = a.nb > 1 ? a.aw[row * K + j] : 0.0;
-            s[2][j] = a.nb > 2 ? a.p[row * K + j] : 0.0;
-            t[2][j] = a.nb > 2 ? a.ap[row * K + j] : 0.0;
+        double s[NB][K], t[NB][K];
+        load_row<K>(a.x + row * K, s[0]);
+        load_row<K>(a.ax + row * K, t[0]);
+        if constexpr (NB > 1) {
+            load_row<K>(a.w + row * K, s[1]);
+            load_row<K>(a.aw + row * K, t[1]);
         }
-        double xn[K], axn[K], pn[K], apn[K];
+        if constexpr (NB > 2) {
+            load_row<K>(a.p + row * K, s[2]);
+            load_row<K>(a.ap + row * K, t[2]);
+        }
+        double xn[K], axn[K], pn[K], apn[K], rn[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             double px = 0.0, pa = 0.0;
-            for (int b = 1; b < a.nb; ++b)
+#pragma unroll
+            for (int b = 1; b < NB; ++b)
 #pragma unroll
                 for (int c = 0; c < K; ++c) {
                     const double cf = a.coef[(b * K + c) * K + j];
@@ -164,36 +201,40 @@ __global__ __launch_bounds__(kUpdThreads) void k_lob_update(UpdArgs a, double *_
             axn[j] = xa;
             pn[j] = px;
             apn[j] = pa;
+            rn[j] = xa - a.theta[j] * xx;
+            r2[j] = rn[j] * rn[j];
         }
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const double rj = axn[j] - a.theta[j] * xn[j];
-            a.x[row * K + j] = xn[j];
-            a.ax[row * K + j] = axn[j];
-            a.r[row * K + j] = rj;
-            if (a.nb > 1) {
-                a.p[row * K + j] = pn[j];
-                a.ap[row * K + j] = apn[j];
-            }
-            r2[j] = rj * rj;
+        store_row<K>(a.x + row * K, xn);
+        store_row<K>(a.ax + row * K, axn);
+        store_row<K>(a.r + row * K, rn);
+        if constexpr (NB > 1) {
+            store_row<K>(a.p + row * K, pn);
+            store_row<K>(a.ap + row * K, apn);
         }
     }
-    __shared__ double sh[K][kUpdThreads];
 #pragma unroll
-    for (int j = 0; j < K; ++j) sh[j][threadIdx.x] = r2[j];
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) r2[j] += __shfl_xor(r2[j], off, 64);
+    __shared__ double sh[kUpdThreads / 64][K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < K; ++j) sh[wave][j] = r2[j];
     __syncthreads();
-    for (int h = kUpdThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
+    if ((int)threadIdx.x < K) {
+        double t = sh[0][threadIdx.x];
 #pragma unroll
-            for (int j = 0; j < K; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + h];
-        __syncthreads();
+        for (int w = 1; w < kUpdThreads / 64; ++w) t += sh[w][threadIdx.x];
+        part[(int64_t)blockIdx.x * K + threadIdx.x] = t;
     }
-    if ((int)threadIdx.x < K) part[(int64_t)blockIdx.x * K + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 template <int K>
-void launch_update(const UpdArgs &a, double *part, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_lob_update<K>, dim3(grid), dim3(kUpdThreads), 0, s, a, part);
+void launch_update(const UpdArgs &a, int nb, double *part, int grid, hipStream_t s) {
+    if (nb == 1) hipLaunchKernelGGL((k_lob_update<K, 1>), dim3(grid), dim3(kUpdThreads), 0, s, a, part);
+    else if (nb == 2) hipLaunchKernelGGL((k_lob_update<K, 2>), dim3(grid), dim3(kUpdThreads), 0, s, a, part);
+    else hipLaunchKernelGGL((k_lob_update<K, 3>), dim3(grid), dim3(kUpdThreads), 0, s, a, part);
     SAIT_LAUNCH_CHECK();
 }
 
@@ -323,7 +364,7 @@ int gram_grid(int64_t quads) {
 }  // namespace
 
 struct Lobpcg::Bufs {
-    DevBuf ax, w, aw, p, ap, r, gpart, upart, small;
+    DevBuf x, ax, w, aw, p, ap, r, gpart, upart, small;  // x: aligned working copy of X
     double *host = nullptr;  // pinned: 2 tiles + K norms
     ~Bufs() {
         if (host) (void)hipHostFree(host);
@@ -342,8 +383,9 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
     if (!X || !lambda) fail(SAIT_E_INVALID, "null X or lambda");
     const size_t blk = (size_t)n * k * sizeof(double);
     Bufs &B = *b_;
-    for (DevBuf *d : {&B.ax, &B.w, &B.aw, &B.p, &B.ap, &B.r})
+    for (DevBuf *d : {&B.x, &B.ax, &B.w, &B.aw, &B.p, &B.ap, &B.r})
         if (d->bytes() < blk) d->alloc(alloc, blk);
+    double *Xi = B.x.as<double>();
     const int64_t quads = (n + 3) / 4;
     const int ggrid = gram_grid(quads);
     const int ugrid = (int)((n + kUpdThreads - 1) / kUpdThreads);
@@ -364,7 +406,7 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
 
     auto gram = [&](int nb) {
         GramArgs g{};
-        g.s[0] = X;
+        g.s[0] = Xi;
         g.s[1] = B.w.as<double>();
         g.s[2] = B.p.as<double>();
         g.as[0] = B.ax.as<double>();
@@ -393,7 +435,7 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         std::copy(theta.begin(), theta.end(), hc + (dtheta - dcoef));
         SAIT_HIP(hipMemcpyAsync(dcoef, hc, (size_t)((dtheta - dcoef) + k) * sizeof(double), hipMemcpyHostToDevice, s));
         UpdArgs u{};
-        u.x = X;
+        u.x = Xi;
         u.ax = B.ax.as<double>();
         u.w = B.w.as<double>();
         u.aw = B.aw.as<double>();
@@ -403,20 +445,20 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         u.coef = dcoef;
         u.theta = dtheta;
         u.n = n;
-        u.nb = nb;
         switch (k) {
-        case 1: launch_update<1>(u, B.upart.as<double>(), ugrid, s); break;
-        case 2: launch_update<2>(u, B.upart.as<double>(), ugrid, s); break;
-        case 3: launch_update<3>(u, B.upart.as<double>(), ugrid, s); break;
-        case 4: launch_update<4>(u, B.upart.as<double>(), ugrid, s); break;
-        default: launch_update<5>(u, B.upart.as<double>(), ugrid, s); break;
+        case 1: launch_update<1>(u, nb, B.upart.as<double>(), ugrid, s); break;
+        case 2: launch_update<2>(u, nb, B.upart.as<double>(), ugrid, s); break;
+        case 3: launch_update<3>(u, nb, B.upart.as<double>(), ugrid, s); break;
+        case 4: launch_update<4>(u, nb, B.upart.as<double>(), ugrid, s); break;
+        default: launch_update<5>(u, nb, B.upart.as<double>(), ugrid, s); break;
         }
         hipLaunchKernelGGL(k_sum_partials, dim3(k), dim3(256), 0, s, B.upart.as<double>(), ugrid, k, dnorm);
         SAIT_LAUNCH_CHECK();
     };
 
     // Rayleigh-Ritz on span(X0)
-    applyA(X, B.ax.as<double>(), s);
+    SAIT_HIP(hipMemcpyAsync(Xi, X, blk, hipMemcpyDeviceToDevice, s));
+    applyA(Xi, B.ax.as<double>(), s);
     gram(1);
     readback(false);
     std::vector<double> theta, coef;
@@ -457,6 +499,8 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         update(use, theta, coef);
         has_p = true;
     }
+    SAIT_HIP(hipMemcpyAsync(X, Xi, blk, hipMemcpyDeviceToDevice, s));
+    SAIT_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < k; ++j) lambda[j] = theta[j];
     if (info) {
         info->iterations = it;

@@ -83,24 +83,50 @@ def test_apply_f64(name, maker, tau, m, lanes):
         pre.close()
 
 
-@pytest.mark.parametrize("nrhs", [2, 3, 8, 11])
-def test_apply_block(nrhs):
-    print(f"[test_apply_block] nrhs={nrhs}", flush=True)
+@pytest.mark.parametrize("nrhs,shape", [(2, -64), (3, -64), (4, -64), (5, -65), (8, -64), (4, 8), (11, -64)])
+def test_apply_block(nrhs, shape):
+    # sliced-ELL blocks (2..5, 8 right-hand sides): every column bit for bit
+    # the oracle's FP64 apply; other shapes / widths: the wavefront kernel
+    print(f"[test_apply_block] nrhs={nrhs} shape={shape}", flush=True)
+    from paper_2106_12836_amd import sait_set_apply_lanes
     A = config("c3", small=True)["A"]
     L, U, ML, MU = _factors(A, 1e-3, 3)
     pre = SaitPreconditioner(A, m=3, tau=1e-3)
     try:
+        sait_set_apply_lanes(pre.handle, shape, shape)
         R = uniform_vector(A.n, 3, k=nrhs)
         Z = pre.apply(_t(R)).cpu().numpy()
         for k in range(nrhs):
             zr = oracle.apply(ML, MU, R[:, k])
-            assert np.linalg.norm(Z[:, k] - zr) <= 1e-12 * np.linalg.norm(zr)
+            if shape < 0 and nrhs in (2, 3, 4, 5, 8):
+                np.testing.assert_array_equal(Z[:, k], zr)
+            else:
+                assert np.linalg.norm(Z[:, k] - zr) <= 1e-12 * np.linalg.norm(zr)
+    finally:
+        pre.close()
+
+
+def test_matvec_block_sliced():
+    # A X with the sliced-ELL block kernel: each column equals scipy's
+    # product up to rounding and the one-vector device product bit for bit
+    print("[test_matvec_block_sliced]", flush=True)
+    from paper_2106_12836_amd import sait_set_apply_lanes
+    A = config("c3", small=True)["A"]
+    pre = SaitPreconditioner(A, m=3, tau=1e-3)
+    try:
+        R = uniform_vector(A.n, 4, k=4)
+        Y = pre.matvec(_t(R)).cpu().numpy()
+        for k in range(4):
+            y1 = pre.matvec(_t(np.ascontiguousarray(R[:, k]))).cpu().numpy()
+            np.testing.assert_array_equal(Y[:, k], y1)
+            ys = A.to_scipy() @ R[:, k]
+            assert np.linalg.norm(Y[:, k] - ys) <= 1e-14 * np.linalg.norm(ys)
     finally:
         pre.close()
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("nrhs,shape", [(1, -64), (1, -65), (1, -8), (1, -16), (4, -16)])
+@pytest.mark.parametrize("nrhs,shape", [(1, -64), (1, -65), (1, -8), (1, -16), (4, -16), (4, -64), (3, -65)])
 def test_apply_mixed_bound(prec, nrhs, shape):
     print(f"[test_apply_mixed_bound] {prec} nrhs={nrhs} shape={shape}", flush=True)
     A = config("c3", small=True)["A"]
@@ -122,8 +148,8 @@ def test_apply_mixed_bound(prec, nrhs, shape):
             bound = 2 * gam * (abs(_sp(MU, f2)) @ (abs(_sp(ML, f1)) @ np.abs(r32))) * (1 + 4 * u)
             assert np.all(np.abs(Z[:, k] - zstar) <= bound)
             zo = oracle.apply_f32acc(ML, f1.astype(np.float32), MU, f2.astype(np.float32), R[:, k])
-            if nrhs == 1:
-                # LDS-staged kernel: binary32 products and sums in the oracle's order
+            if nrhs == 1 or shape < 0:
+                # binary32 products and sums in the oracle's order
                 np.testing.assert_array_equal(Z[:, k], zo)
             assert np.linalg.norm(Z[:, k] - zo) <= 1e-5 * np.linalg.norm(zo)
     finally:
