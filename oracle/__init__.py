@@ -54,6 +54,8 @@ def lib():
         L.or_ilu0.argtypes = [I64, _i32p, _i32p, _f64p, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_ilut.argtypes = [I64, _i32p, _i32p, _f64p, D, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_iluk.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
+        L.or_iluk_pattern.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d]
+        L.or_parilu.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_lower_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_upper_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_sait_step.argtypes = [I64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, D, C.c_int, C.c_int, pp_i, pp_i,
@@ -147,6 +149,26 @@ def iluk(A: Csr, p: int):
     st = lib().or_iluk(A.n, rp, ci, v, int(p), *(C.byref(x) for x in Lo), *(C.byref(x) for x in Uo))
     _check(st, "iluk")
     return _take(A.n, *Lo), _take(A.n, *Uo)
+
+
+def iluk_pattern(A: Csr, p: int) -> Csr:
+    """The level-p pattern of A as a matrix: A's values, explicit zeros at
+    the kept fill."""
+    keep, (rp, ci, v) = _csr_args(A)
+    E = _out3()
+    _check(lib().or_iluk_pattern(A.n, rp, ci, v, int(p), *(C.byref(x) for x in E)), "iluk_pattern")
+    return _take(A.n, *E)
+
+
+def parilu(A: Csr, sweeps: int, level: int = 0):
+    """Fine-grained parallel ILU (Chow and Patel), synchronous sweeps on the
+    level-`level` pattern of A (0: A's own pattern).  Returns (L, U)."""
+    E = A if level == 0 else iluk_pattern(A, level)
+    keep, (rp, ci, v) = _csr_args(E)
+    Lo, Uo = _out3(), _out3()
+    st = lib().or_parilu(E.n, rp, ci, v, int(sweeps), *(C.byref(x) for x in Lo), *(C.byref(x) for x in Uo))
+    _check(st, "parilu")
+    return _take(E.n, *Lo), _take(E.n, *Uo)
 
 
 def lower_solve(L: Csr, b):

@@ -236,9 +236,10 @@ static int32_t heap_pop(int32_t *h, int64_t *cnt) {
     return top;
 }
 
-int or_iluk(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int p,
-            int32_t **Lrp, int32_t **Lci, double **Lv,
-            int32_t **Urp, int32_t **Uci, double **Uv) {
+/* The level-p pattern of A (the extended matrix E: A's values, 0 at the
+ * kept fill); or_iluk factors E by ILU(0), or_parilu iterates on it. */
+int or_iluk_pattern(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int p,
+                    int32_t **Erp, int32_t **Eci, double **Ev) {
     if (p < 0) return OR_E_INVALID;
     const int INF = 0x7fffffff;
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -322,10 +323,149 @@ int or_iluk(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, in
         erp[i + 1] = (int32_t)ecnt;
         uptr[i + 1] = ucnt;
     }
-    if (st == OR_OK) st = or_ilu0(n, erp, eci, ev, Lrp, Lci, Lv, Urp, Uci, Uv);
 out:
-    free(lev); free(heap); free(act); free(uptr); free(ucol); free(ulev);
-    free(erp); free(eci); free(ev); free(wv);
+    free(lev); free(heap); free(act); free(uptr); free(ucol); free(ulev); free(wv);
+    if (st == OR_OK) {
+        *Erp = erp; *Eci = eci; *Ev = ev;
+    } else {
+        free(erp); free(eci); free(ev);
+    }
+    return st;
+}
+
+int or_iluk(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int p,
+            int32_t **Lrp, int32_t **Lci, double **Lv,
+            int32_t **Urp, int32_t **Uci, double **Uv) {
+    int32_t *erp = NULL, *eci = NULL;
+    double *ev = NULL;
+    int st = or_iluk_pattern(n, rp, ci, v, p, &erp, &eci, &ev);
+    if (st == OR_OK) st = or_ilu0(n, erp, eci, ev, Lrp, Lci, Lv, Urp, Uci, Uv);
+    free(erp); free(eci); free(ev);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Fine-grained parallel ILU (Chow and Patel, SIAM J. Sci. Comput. 37    */
+/* (2015); cited in the introduction), synchronous form.                */
+/* ------------------------------------------------------------------ */
+
+/* Position of column j in the sorted row [b, e) of ci, or -1. */
+static int64_t find_col(const int32_t *ci, int64_t b, int64_t e, int32_t j) {
+    while (b < e) {
+        int64_t m = (b + e) / 2;
+        if (ci[m] == j) return m;
+        if (ci[m] < j) b = m + 1;
+        else e = m;
+    }
+    return -1;
+}
+
+/*
+ * ILU factors on the pattern S of the given matrix (values a_ij, explicit
+ * zeros at fill) as the fixed point of
+ *     u_ij = a_ij - sum_{k < i} l_ik u_kj                 (i <= j)
+ *     l_ij = (a_ij - sum_{k < j} l_ik u_kj) / u_jj        (i > j)
+ * with all k such that (i,k) and (k,j) lie in S.  Each sweep recomputes
+ * every entry from the previous sweep's L and U (Jacobi-like), subtracting
+ * the products in increasing k with separate roundings.  Start: l_ij =
+ * a_ij / a_jj, u_ij = a_ij.  With enough sweeps (the depth of the
+ * dependency graph) the result is the ILU factorisation of S itself.
+ * L is returned unit lower triangular with its diagonal stored.
+ */
+int or_parilu(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int sweeps,
+              int32_t **Lrp, int32_t **Lci, double **Lv,
+              int32_t **Urp, int32_t **Uci, double **Uv) {
+    if (sweeps < 0) return OR_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t nl = 0, nu = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int diag = 0;
+        for (int64_t q = rp[i]; q < rp[i + 1]; q++) {
+            if (ci[q] < i) nl++;
+            else nu++;
+            if (ci[q] == i) diag = (v[q] != 0.0);
+        }
+        if (!diag) return OR_E_ZERO_PIVOT;
+    }
+    int32_t *lrp = (int32_t *)malloc(sizeof(int32_t) * (nn + 1));
+    int32_t *lci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nl + n + 1));
+    double *la = (double *)malloc(sizeof(double) * (size_t)(nl + 1));
+    double *l0 = (double *)malloc(sizeof(double) * (size_t)(nl + 1));
+    double *l1 = (double *)malloc(sizeof(double) * (size_t)(nl + 1));
+    int32_t *urp = (int32_t *)malloc(sizeof(int32_t) * (nn + 1));
+    int32_t *uci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nu + 1));
+    double *ua = (double *)malloc(sizeof(double) * (size_t)(nu + 1));
+    double *u0 = (double *)malloc(sizeof(double) * (size_t)(nu + 1));
+    double *u1 = (double *)malloc(sizeof(double) * (size_t)(nu + 1));
+    int st = OR_OK;
+    if (!lrp || !lci || !la || !l0 || !l1 || !urp || !uci || !ua || !u0 || !u1) { st = OR_E_NOMEM; goto out; }
+    /* strictly lower part (the unit diagonal is added at the end) and upper part */
+    {
+        int64_t a = 0, b = 0;
+        lrp[0] = 0;
+        urp[0] = 0;
+        for (int64_t i = 0; i < n; i++) {
+            for (int64_t q = rp[i]; q < rp[i + 1]; q++) {
+                if (ci[q] < i) { lci[a] = ci[q]; la[a] = v[q]; a++; }
+                else { uci[b] = ci[q]; ua[b] = v[q]; b++; }
+            }
+            lrp[i + 1] = (int32_t)a;
+            urp[i + 1] = (int32_t)b;
+        }
+    }
+    for (int64_t e = 0; e < nu; e++) u0[e] = ua[e];
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t e = lrp[i]; e < lrp[i + 1]; e++) l0[e] = la[e] / ua[urp[lci[e]]];  /* a_ij / a_jj */
+    for (int s = 0; s < sweeps; s++) {
+        for (int64_t i = 0; i < n; i++) {
+            /* L entries (i, j), j < i */
+            for (int64_t e = lrp[i]; e < lrp[i + 1]; e++) {
+                int32_t j = lci[e];
+                double t = la[e];
+                for (int64_t q = lrp[i]; q < lrp[i + 1] && lci[q] < j; q++) {
+                    int32_t k = lci[q];
+                    int64_t f = find_col(uci, urp[k], urp[k + 1], j);
+                    if (f >= 0) t = t - l0[q] * u0[f];
+                }
+                l1[e] = t / u0[urp[j]];
+            }
+            /* U entries (i, j), j >= i */
+            for (int64_t e = urp[i]; e < urp[i + 1]; e++) {
+                int32_t j = uci[e];
+                double t = ua[e];
+                for (int64_t q = lrp[i]; q < lrp[i + 1]; q++) {
+                    int32_t k = lci[q];
+                    int64_t f = find_col(uci, urp[k], urp[k + 1], j);
+                    if (f >= 0) t = t - l0[q] * u0[f];
+                }
+                u1[e] = t;
+            }
+        }
+        double *tl = l0; l0 = l1; l1 = tl;
+        double *tu = u0; u0 = u1; u1 = tu;
+    }
+    for (int64_t e = 0; e < nl; e++) if (!isfinite(l0[e])) st = OR_E_NONFINITE;
+    for (int64_t e = 0; e < nu; e++) if (!isfinite(u0[e])) st = OR_E_NONFINITE;
+    if (st != OR_OK) goto out;
+    /* outputs: L with its unit diagonal, U as computed */
+    {
+        or_builder Lb, Ub;
+        st = bld_init(&Lb, n, nl + n);
+        if (st == OR_OK) st = bld_init(&Ub, n, nu);
+        if (st != OR_OK) goto out;
+        for (int64_t i = 0; i < n; i++) {
+            for (int64_t e = lrp[i]; e < lrp[i + 1]; e++) bld_push(&Lb, lci[e], l0[e]);
+            bld_push(&Lb, (int32_t)i, 1.0);
+            bld_end_row(&Lb, i);
+            for (int64_t e = urp[i]; e < urp[i + 1]; e++) bld_push(&Ub, uci[e], u0[e]);
+            bld_end_row(&Ub, i);
+        }
+        bld_give(&Lb, Lrp, Lci, Lv);
+        bld_give(&Ub, Urp, Uci, Uv);
+    }
+out:
+    free(lrp); free(lci); free(la); free(l0); free(l1);
+    free(urp); free(uci); free(ua); free(u0); free(u1);
     return st;
 }
 
