@@ -21,7 +21,9 @@ triangular solves and no preconditioner: iterations and seconds per solve.
 `eigen_experiment`: the paper's LOBPCG experiment (the 4 smallest
 eigenpairs of the same matrix, SAIT_Thr(0.01, 10) block preconditioning,
 beside the exact solves and none): steps, seconds, error against the
-closed-form spectrum.
+closed-form spectrum.  `parilu_experiment`: the ILU factors built on the
+device by fine-grained parallel ILU sweeps: build time and PCG iterations
+against the host ILU(0).
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -372,6 +374,50 @@ def paper_experiment(torch, dev):
     return out
 
 
+def parilu_experiment(torch, dev):
+    """ILU factors built on the device by synchronous fixed-point sweeps
+    (fine-grained parallel ILU) instead of the row-wise host ILU(0), on the
+    paper's 100^3 problem, for 1, 2, 3 and 5 sweeps on the ILU(0) pattern
+    beside the host ILU(0): build time with m = 0 (the factorisation and the
+    device copies, no Horner passes) and with SAIT_Thr(0.02, 10); GMRES(30)
+    and PCG iterations to 1e-10 (f ~ U[0, 1), seed 0) with that SAIT
+    preconditioner.  GMRES takes any preconditioner; PCG needs a symmetric
+    one, which intermediate synchronous sweeps do not give (each sweep
+    divides by the previous sweep's pivots)."""
+    from paper_2106_12836_amd import SaitPreconditioner
+    from workloads import poisson3d
+
+    A = poisson3d(100)
+    f = torch.tensor(np.random.default_rng(0).uniform(0.0, 1.0, A.n), dtype=torch.float64, device=dev)
+
+    def build(**opts):
+        SaitPreconditioner(A, **opts).close()  # warm-up (first-use allocations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pre = SaitPreconditioner(A, **opts)
+        torch.cuda.synchronize()
+        return pre, time.perf_counter() - t0
+
+    def run(**ilu):
+        pre0, t0 = build(m=0, tau=0.02, **ilu)
+        pre0.close()
+        pre, tb = build(m=10, tau=0.02, **ilu)
+        x, (gi,) = pre.solve(f, rtol=1e-10, method="gmres", restart=30, maxit=5000)
+        x, (pi,) = pre.solve(f, rtol=1e-10, method="pcg", maxit=5000)
+        rec = dict(build_m0_s=round(t0, 4), build_s=round(tb, 4), ratio_L=round(pre.query()["ratio_L"], 4),
+                   gmres_iterations=gi.iterations, gmres_status=gi.status, pcg_iterations=pi.iterations,
+                   pcg_status=pi.status)
+        pre.close()
+        return rec
+
+    out = dict(workload="3D 7-point Laplace 100^3, SAIT_Thr(0.02, 10), GMRES(30) / PCG to 1e-10, f ~ U[0,1) "
+                        "(seed 0)", host_ilu0=run())
+    for sw in (1, 2, 3, 5):
+        out[f"parilu_{sw}"] = run(ilu_kind="parilu", ilu_level=0, parilu_sweeps=sw)
+    print(f"[bench] parilu: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def eigen_experiment(torch, dev, levels=(0, 1), comparators=True):
     """The paper's eigenvalue experiment (Sec. 4): the 4 smallest eigenpairs
     of the 7-point Laplacian on the 100^3 interior by LOBPCG, preconditioned
@@ -438,6 +484,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads (rdd, c2, c5)")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's PCG experiment (100^3)")
     ap.add_argument("--no-eigen", action="store_true", help="skip the paper's LOBPCG experiment (100^3)")
+    ap.add_argument("--no-parilu", action="store_true", help="skip the device ILU (ParILU) experiment (100^3)")
+    ap.add_argument("--parilu-only", action="store_true",
+                    help="run only the device ILU (ParILU) experiment and print its record (for profiling)")
     ap.add_argument("--eigen-only", action="store_true",
                     help="run only the level-0 SAIT LOBPCG solve and print its record (for profiling)")
     ap.add_argument("--batched-only", action="store_true",
@@ -458,6 +507,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.batched_only:
         print(json.dumps({"batched": batched_solve(torch, dev)}), flush=True)
+        return
+    if args.parilu_only:
+        print(json.dumps({"parilu_experiment": parilu_experiment(torch, dev)}), flush=True)
         return
     if args.eigen_only:
         print(json.dumps({"eigen_experiment": eigen_experiment(torch, dev, levels=(0,), comparators=False)}),
@@ -567,6 +619,9 @@ def main():
     eigen = None
     if not args.no_eigen:
         eigen = eigen_experiment(torch, dev)
+    parilu = None
+    if not args.no_parilu:
+        parilu = parilu_experiment(torch, dev)
 
     batched = None
     if not args.no_batched:
@@ -607,6 +662,7 @@ def main():
         "other_workloads": extra,
         "paper_experiment": paper,
         "eigen_experiment": eigen,
+        "parilu_experiment": parilu,
     }
     print(json.dumps(line), flush=True)
 

@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.cpp", "ilu_host.cpp", "k_spgemm.hip", "k_spmv.hip", "k_krylov.hip", "k_batched.hip",
-           "k_precond.hip", "k_lobpcg.hip"]
+           "k_precond.hip", "k_lobpcg.hip", "k_parilu.hip"]
 EXTRA = {"ilu_host.cpp": ["-ffp-contract=off"]}
 
 

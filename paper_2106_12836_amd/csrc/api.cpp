@@ -205,6 +205,7 @@ void sait_default_build_opts(sait_build_opts *o) {
     o->precision = SAIT_F64;
     o->build_transpose = 0;
     o->upper_side = SAIT_SIDE_RIGHT;
+    o->parilu_sweeps = 3;
 }
 
 void sait_default_solve_opts(sait_solve_opts *o) {
@@ -227,9 +228,12 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         sait_build_opts opts;
         sait_default_build_opts(&opts);
         if (o) opts = *o;
-        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT && opts.ilu_kind != SAIT_ILUK)
+        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT && opts.ilu_kind != SAIT_ILUK &&
+            opts.ilu_kind != SAIT_PARILU)
             fail(SAIT_E_INVALID, "unknown ilu_kind");
-        if (opts.ilu_kind == SAIT_ILUK && opts.ilu_level < 0) fail(SAIT_E_INVALID, "ilu_level must be >= 0");
+        if ((opts.ilu_kind == SAIT_ILUK || opts.ilu_kind == SAIT_PARILU) && opts.ilu_level < 0)
+            fail(SAIT_E_INVALID, "ilu_level must be >= 0");
+        if (opts.ilu_kind == SAIT_PARILU && opts.parilu_sweeps < 0) fail(SAIT_E_INVALID, "parilu_sweeps must be >= 0");
         if (opts.upper_side != SAIT_SIDE_LEFT && opts.upper_side != SAIT_SIDE_RIGHT)
             fail(SAIT_E_INVALID, "upper_side must be SAIT_SIDE_LEFT or SAIT_SIDE_RIGHT");
         if (opts.precision != SAIT_F64 && opts.precision != SAIT_F32 && opts.precision != SAIT_BF16)
@@ -270,11 +274,20 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         h->A_h.rp.assign(row_ptr, row_ptr + n + 1);
         h->A_h.ci.assign(col_idx, col_idx + row_ptr[n]);
         h->A_h.v.assign(val, val + row_ptr[n]);
+        hipStream_t s = as_stream(hip_stream);
         if (opts.ilu_kind == SAIT_ILU0) host_ilu0(h->A_h, h->L_h, h->U_h);
         else if (opts.ilu_kind == SAIT_ILUK) host_iluk(h->A_h, opts.ilu_level, h->L_h, h->U_h);
+        else if (opts.ilu_kind == SAIT_PARILU) {
+            if (opts.ilu_level == 0) {
+                parilu_device(&h->alloc, h->A_h, opts.parilu_sweeps, h->L_h, h->U_h, s);
+            } else {
+                HostCsr E;
+                host_iluk_pattern(h->A_h, opts.ilu_level, E);
+                parilu_device(&h->alloc, E, opts.parilu_sweeps, h->L_h, h->U_h, s);
+            }
+        }
         else host_ilut(h->A_h, opts.ilut_tau, opts.ilut_fill, h->L_h, h->U_h);
 
-        hipStream_t s = as_stream(hip_stream);
         upload_csr(&h->alloc, h->A_h, h->A, s);
         SaitParams p;
         p.m = opts.m;

@@ -221,7 +221,7 @@ void host_ilut(const HostCsr &A, double tau, int fill, HostCsr &L, HostCsr &U) {
 // for every j > k of row k of U at level lev(i,k) + lev(k,j) + 1; positions
 // reached at a level <= p form the pattern, and the factors are the ILU(0)
 // elimination over it (A's values there, zeros at the fill positions).
-void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U) {
+void host_iluk_pattern(const HostCsr &A, int level, HostCsr &E) {
     if (level < 0) fail(SAIT_E_INVALID, "ILU(k): level must be >= 0");
     const int64_t n = A.n;
     constexpr int kNone = std::numeric_limits<int>::max();
@@ -229,7 +229,7 @@ void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U) {
     std::vector<int32_t> upos(n + 1, 0);   // U-part (columns > row) levels of finished rows
     std::vector<int32_t> ucol;
     std::vector<int> ulev;
-    HostCsr E;                               // A on the level-p pattern
+    E = HostCsr{};                           // A on the level-p pattern
     E.n = n;
     E.rp.assign(n + 1, 0);
     std::vector<int32_t> row;
@@ -275,6 +275,11 @@ void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U) {
         E.rp[i + 1] = (int32_t)E.ci.size();
         upos[i + 1] = (int32_t)ucol.size();
     }
+}
+
+void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U) {
+    HostCsr E;
+    host_iluk_pattern(A, level, E);
     host_ilu0(E, L, U);
 }
 

@@ -114,6 +114,12 @@ void validate_csr(int64_t n, const int32_t *rp, const int32_t *ci, const double 
 void host_ilu0(const HostCsr &A, HostCsr &L, HostCsr &U);
 void host_ilut(const HostCsr &A, double tau, int fill, HostCsr &L, HostCsr &U);
 void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U);
+// A on its level-p pattern: A's values, explicit zeros at the kept fill.
+void host_iluk_pattern(const HostCsr &A, int level, HostCsr &E);
+// Fine-grained parallel ILU on the pattern of E: `sweeps` synchronous
+// fixed-point sweeps on the device (k_parilu.hip); L unit lower with its
+// diagonal stored, U upper.
+void parilu_device(Allocator *a, const HostCsr &E, int sweeps, HostCsr &L, HostCsr &U, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // SpGEMM construction of the SAIT factors (k_spgemm.hip)

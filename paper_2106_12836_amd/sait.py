@@ -21,7 +21,7 @@ _LIB = None
 
 SAIT_OK, SAIT_NOT_CONVERGED, SAIT_BREAKDOWN = 0, 1, 2
 SAIT_E_INVALID, SAIT_E_ZERO_PIVOT, SAIT_E_NONFINITE, SAIT_E_NOMEM, SAIT_E_DEVICE = -1, -2, -3, -4, -5
-SAIT_ILU0, SAIT_ILUT, SAIT_ILUK = 0, 1, 2
+SAIT_ILU0, SAIT_ILUT, SAIT_ILUK, SAIT_PARILU = 0, 1, 2, 3
 SAIT_SIDE_LEFT, SAIT_SIDE_RIGHT = 0, 1
 SIDES = {"left": SAIT_SIDE_LEFT, "right": SAIT_SIDE_RIGHT}
 SAIT_METHOD_GMRES, SAIT_METHOD_PCG = 0, 1
@@ -56,6 +56,7 @@ class sait_build_opts(C.Structure):
         ("pattern_p", C.c_int), ("precision", C.c_int), ("build_transpose", C.c_int),
         ("ilu_level", C.c_int),
         ("upper_side", C.c_int),
+        ("parilu_sweeps", C.c_int),
     ]
 
 
@@ -160,7 +161,7 @@ def default_build_opts(**kw) -> sait_build_opts:
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
         if k == "ilu_kind" and isinstance(v, str):
-            v = {"ilu0": SAIT_ILU0, "ilut": SAIT_ILUT, "iluk": SAIT_ILUK}[v]
+            v = {"ilu0": SAIT_ILU0, "ilut": SAIT_ILUT, "iluk": SAIT_ILUK, "parilu": SAIT_PARILU}[v]
         if k == "upper_side" and isinstance(v, str):
             v = SIDES[v]
         setattr(o, k, v)
@@ -361,7 +362,8 @@ class SaitPreconditioner:
     A: any object with ``n``, ``rp``, ``ci``, ``v`` (e.g. workloads.Csr) or
     a scipy sparse matrix.  Keyword options mirror sait_build_opts
     (ilu_kind, ilut_tau, ilut_fill, m, tau, max_nnz_row, pattern_p,
-    precision, build_transpose, ilu_level, upper_side: "right" or "left").
+    precision, build_transpose, ilu_level, upper_side: "right" or "left",
+    parilu_sweeps).
     """
 
     def __init__(self, A, nsys: int = 1, sys_ptr=None, stream=None, **opts):

@@ -86,7 +86,7 @@ def test_build_opts_layout_matches_header(lib):
     o = S.default_build_opts()
     assert (o.ilu_kind, o.ilut_tau, o.ilut_fill, o.m, o.tau) == (S.SAIT_ILU0, 1e-3, 10, 3, 1e-2)
     assert (o.max_nnz_row, o.pattern_p, o.precision, o.build_transpose) == (0, -1, S.SAIT_F64, 0)
-    assert (o.ilu_level, o.upper_side) == (1, S.SAIT_SIDE_RIGHT)
+    assert (o.ilu_level, o.upper_side, o.parilu_sweeps) == (1, S.SAIT_SIDE_RIGHT, 3)
     s = S.default_solve_opts()
     assert (s.restart, s.maxit, s.rtol, s.flexible, s.method) == (30, 10000, 1e-8, 0, 0)
     assert S.default_build_opts(upper_side="left").upper_side == S.SAIT_SIDE_LEFT

@@ -29,11 +29,13 @@ def _cmp_csr(rp, ci, v, ref: Csr, what):
     assert err.max(initial=0.0) <= RTOL, f"{what}: max rel err {err.max()}"
 
 
-def _oracle_factors(A, ilu, m, tau, cap=0, p=-1, ilut=(1e-3, 10), level=1, upper_side="right"):
+def _oracle_factors(A, ilu, m, tau, cap=0, p=-1, ilut=(1e-3, 10), level=1, upper_side="right", sweeps=3):
     if ilu == "ilu0":
         L, U = oracle.ilu0(A)
     elif ilu == "iluk":
         L, U = oracle.iluk(A, level)
+    elif ilu == "parilu":
+        L, U = oracle.parilu(A, sweeps, level)
     else:
         L, U = oracle.ilut(A, *ilut)
     if p >= 0:
@@ -52,6 +54,11 @@ CASES = [
     ("poisson3d-ilu1", lambda: poisson3d(10), dict(m=10, tau=0.02, ilu_kind="iluk", ilu_level=1)),
     ("rdd-ilu2", lambda: random_diag_dominant(1500, 8, band=120, seed=6), dict(m=3, tau=1e-2, ilu_kind="iluk",
                                                                                 ilu_level=2)),
+    ("p3d-parilu3", lambda: poisson3d(9), dict(m=3, tau=1e-2, ilu_kind="parilu", ilu_level=0, parilu_sweeps=3)),
+    ("rdd-parilu0", lambda: random_diag_dominant(2000, 8, band=150, seed=11), dict(m=3, tau=1e-2, ilu_kind="parilu",
+                                                                                  ilu_level=0, parilu_sweeps=0)),
+    ("convdiff-parilu-l1", lambda: convdiff2d_upwind(30, 10.0), dict(m=4, tau=1e-3, ilu_kind="parilu", ilu_level=1,
+                                                                      parilu_sweeps=2)),
     ("cap5", lambda: poisson3d(7), dict(m=4, tau=0.0, max_nnz_row=5)),
     ("rdd-cap6", lambda: random_diag_dominant(1200, 8, band=90, seed=8), dict(m=3, tau=1e-3, max_nnz_row=6)),
     ("pat2", lambda: poisson3d(8), dict(m=3, tau=0.0, pattern_p=2)),
@@ -71,7 +78,7 @@ def test_factors_match_oracle(name, maker, opts):
     ilu = opts.get("ilu_kind", "ilu0")
     L, U, ML, MU = _oracle_factors(A, ilu, opts["m"], opts["tau"], opts.get("max_nnz_row", 0),
                                    opts.get("pattern_p", -1), level=opts.get("ilu_level", 1),
-                                   upper_side=opts.get("upper_side", "right"))
+                                   upper_side=opts.get("upper_side", "right"), sweeps=opts.get("parilu_sweeps", 3))
     pre = SaitPreconditioner(A, **opts)
     try:
         for which, ref in (("L", L), ("U", U)):
@@ -208,4 +215,38 @@ def test_build_errors():
     nanA.v[0] = np.nan
     with pytest.raises(SaitError) as e:
         SaitPreconditioner(nanA)
+    assert e.value.status == -3
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_parilu_reaches_the_ilu_factors(level):
+    # enough synchronous sweeps on the device give the row-wise ILU(0) /
+    # ILU(1) factors bit for bit (the same formula, products in the same order)
+    print(f"[test_parilu_reaches_the_ilu_factors] level={level}", flush=True)
+    A = random_diag_dominant(400, 6, band=40, seed=12)
+    pre = SaitPreconditioner(A, m=2, tau=1e-2, ilu_kind="parilu", ilu_level=level, parilu_sweeps=A.n)
+    try:
+        L0, U0 = oracle.ilu0(A) if level == 0 else oracle.iluk(A, level)
+        for which, ref in (("L", L0), ("U", U0)):
+            rp, ci, v = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v, ref.v)
+    finally:
+        pre.close()
+
+
+def test_parilu_errors():
+    print("[test_parilu_errors]", flush=True)
+    with pytest.raises(SaitError):
+        SaitPreconditioner(poisson2d(5), ilu_kind="parilu", parilu_sweeps=-1)
+    A = Csr(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([0.0, 1.0, 1.0, 2.0]))
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(A, ilu_kind="parilu", ilu_level=0)
+    assert e.value.status == -2
+    # a matrix whose sweeps overflow: huge off-diagonals against tiny pivots
+    B = Csr(3, np.array([0, 2, 5, 7], np.int32), np.array([0, 1, 0, 1, 2, 1, 2], np.int32),
+            np.array([1e-300, 1e300, 1e300, 1e-300, 1e300, 1e300, 1e-300]))
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(B, ilu_kind="parilu", ilu_level=0, parilu_sweeps=2)
     assert e.value.status == -3
