@@ -71,6 +71,10 @@ struct sait_handle_s {
     std::vector<int64_t> sys_ptr;
     sait_build_opts opts{};
     HostCsr A_h, L_h, U_h;
+    // device ILU: the factors stay on the device; L_h / U_h are filled on
+    // first use (export, Jacobi / exact preconditioners)
+    DevCsr Ld, Ud;
+    bool host_lu = true;
     DevCsr A, ML, MU, At, MLt, MUt;
     bool has_transpose = false;
     int lanesA = 8, lanesL = 8, lanesU = 8, lanesAt = 8, lanesLt = 8, lanesUt = 8;
@@ -89,6 +93,13 @@ struct sait_handle_s {
 };
 
 namespace {
+
+void ensure_host_lu(sait_handle h) {
+    if (h->host_lu) return;
+    download_csr(h->Ld, h->L_h, nullptr);
+    download_csr(h->Ud, h->U_h, nullptr);
+    h->host_lu = true;
+}
 
 template <class F> int guard(F &&f) {
     try {
@@ -275,20 +286,23 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         h->A_h.ci.assign(col_idx, col_idx + row_ptr[n]);
         h->A_h.v.assign(val, val + row_ptr[n]);
         hipStream_t s = as_stream(hip_stream);
+        upload_csr(&h->alloc, h->A_h, h->A, s);
         if (opts.ilu_kind == SAIT_ILU0) host_ilu0(h->A_h, h->L_h, h->U_h);
         else if (opts.ilu_kind == SAIT_ILUK) host_iluk(h->A_h, opts.ilu_level, h->L_h, h->U_h);
         else if (opts.ilu_kind == SAIT_PARILU) {
             if (opts.ilu_level == 0) {
-                parilu_device(&h->alloc, h->A_h, opts.parilu_sweeps, h->L_h, h->U_h, s);
+                parilu_device(&h->alloc, h->A, opts.parilu_sweeps, h->Ld, h->Ud, s);
             } else {
                 HostCsr E;
                 host_iluk_pattern(h->A_h, opts.ilu_level, E);
-                parilu_device(&h->alloc, E, opts.parilu_sweeps, h->L_h, h->U_h, s);
+                DevCsr Ed;
+                upload_csr(&h->alloc, E, Ed, s);
+                parilu_device(&h->alloc, Ed, opts.parilu_sweeps, h->Ld, h->Ud, s);
             }
+            h->host_lu = false;
         }
         else host_ilut(h->A_h, opts.ilut_tau, opts.ilut_fill, h->L_h, h->U_h);
 
-        upload_csr(&h->alloc, h->A_h, h->A, s);
         SaitParams p;
         p.m = opts.m;
         p.tau = opts.tau;
@@ -297,15 +311,15 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         p.precision = opts.precision;
         {
             DevCsr T;
-            upload_csr(&h->alloc, h->L_h, T, s);
-            build_sait_factor(&h->alloc, T, p, h->ML, s);
+            if (h->host_lu) upload_csr(&h->alloc, h->L_h, T, s);
+            build_sait_factor(&h->alloc, h->host_lu ? T : h->Ld, p, h->ML, s);
         }
         {
             DevCsr T;
-            upload_csr(&h->alloc, h->U_h, T, s);
+            if (h->host_lu) upload_csr(&h->alloc, h->U_h, T, s);
             SaitParams pu = p;
             pu.right = opts.upper_side == SAIT_SIDE_RIGHT;
-            build_sait_factor(&h->alloc, T, pu, h->MU, s);
+            build_sait_factor(&h->alloc, h->host_lu ? T : h->Ud, pu, h->MU, s);
         }
         if (opts.build_transpose) {
             transpose_csr(&h->alloc, h->A, h->At, s);
@@ -457,6 +471,7 @@ int sait_set_preconditioner(sait_handle h, int kind, int sweeps, void *hip_strea
             if (!h->JL) {
                 auto JL = std::make_unique<JacobiFactor>();
                 auto JU = std::make_unique<JacobiFactor>();
+                ensure_host_lu(h);
                 build_jacobi(&h->alloc, h->L_h, *JL, s);
                 build_jacobi(&h->alloc, h->U_h, *JU, s);
                 h->JL = std::move(JL);
@@ -468,6 +483,7 @@ int sait_set_preconditioner(sait_handle h, int kind, int sweeps, void *hip_strea
             if (!h->EL) {
                 auto EL = std::make_unique<LevelFactor>();
                 auto EU = std::make_unique<LevelFactor>();
+                ensure_host_lu(h);
                 build_levels(&h->alloc, h->L_h, true, *EL, s);
                 build_levels(&h->alloc, h->U_h, false, *EU, s);
                 h->EL = std::move(EL);
@@ -511,8 +527,8 @@ int sait_query(sait_handle h, int64_t *n, int64_t *nnz_A, int64_t *nnz_L, int64_
         if (!h) fail(SAIT_E_INVALID, "null handle");
         if (n) *n = h->n;
         if (nnz_A) *nnz_A = h->A_h.nnz();
-        if (nnz_L) *nnz_L = h->L_h.nnz();
-        if (nnz_U) *nnz_U = h->U_h.nnz();
+        if (nnz_L) *nnz_L = h->host_lu ? h->L_h.nnz() : h->Ld.nnz;
+        if (nnz_U) *nnz_U = h->host_lu ? h->U_h.nnz() : h->Ud.nnz;
         if (nnz_ML) *nnz_ML = h->ML.nnz;
         if (nnz_MU) *nnz_MU = h->MU.nnz;
         return SAIT_OK;
@@ -527,8 +543,14 @@ int sait_export(sait_handle h, int which, int32_t *row_ptr, int32_t *col_idx, do
         const DevCsr *dc = factor_of(h, which);
         switch (which) {
         case SAIT_MAT_A: hc = &h->A_h; break;
-        case SAIT_MAT_L: hc = &h->L_h; break;
-        case SAIT_MAT_U: hc = &h->U_h; break;
+        case SAIT_MAT_L:
+            ensure_host_lu(h);
+            hc = &h->L_h;
+            break;
+        case SAIT_MAT_U:
+            ensure_host_lu(h);
+            hc = &h->U_h;
+            break;
         case SAIT_MAT_ML:
         case SAIT_MAT_MU:
             if (!col_idx && !val) {  // row pointers only: skip the entries

@@ -8,11 +8,12 @@
 // thread each -- from the previous sweep's L and U (double-buffered), the
 // products subtracted in increasing k with separate roundings; the start
 // is l_ij = a_ij / a_jj, u_ij = a_ij.  Deterministic: the factors after s
-// sweeps are the same on every run.  The symbolic pattern stays on the host.
+// sweeps are the same on every run.  The pattern split and the factors stay
+// on the device; a level-k pattern comes from the host's symbolic phase.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
-#include <vector>
 
 #include "sait_internal.h"
 
@@ -94,63 +95,125 @@ __global__ void k_parilu_sweep(Pattern p, const double *__restrict__ l0, const d
     if (check && !isfinite(out)) atomicOr(err, 1);
 }
 
+// Row i's strictly lower and upper counts; err |= 1 without a nonzero
+// diagonal.
+__global__ void k_pl_count(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+                           int64_t *__restrict__ lcnt, int64_t *__restrict__ ucnt, int *__restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int nl = 0, nu = 0;
+    bool diag = false;
+    for (int q = rp[i]; q < rp[i + 1]; ++q) {
+        const int j = ci[q];
+        if (j < i) ++nl;
+        else ++nu;
+        if (j == i) diag = v[q] != 0.0;
+    }
+    lcnt[i] = nl;
+    ucnt[i] = nu;
+    if (!diag) atomicOr(err, 1);
+}
+
+// Split row i of E into its strictly lower and upper parts (the row order
+// of both is E's, i.e. ascending columns).
+__global__ void k_pl_split(int n, const int *__restrict__ rp, const int *__restrict__ ci, const double *__restrict__ v,
+                           const int64_t *__restrict__ lptr, const int64_t *__restrict__ uptr, int *__restrict__ lrp,
+                           int *__restrict__ urp, int *__restrict__ lci, double *__restrict__ la,
+                           int *__restrict__ lrow, int *__restrict__ uci, double *__restrict__ ua,
+                           int *__restrict__ urow) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    lrp[i] = (int)lptr[i];
+    urp[i] = (int)uptr[i];
+    if (i == n) return;
+    int a = (int)lptr[i], b = (int)uptr[i];
+    for (int q = rp[i]; q < rp[i + 1]; ++q) {
+        const int j = ci[q];
+        if (j < i) {
+            lci[a] = j;
+            la[a] = v[q];
+            lrow[a] = i;
+            ++a;
+        } else {
+            uci[b] = j;
+            ua[b] = v[q];
+            urow[b] = i;
+            ++b;
+        }
+    }
+}
+
+// L with its unit diagonal after the row's strictly lower entries.
+__global__ void k_pl_assemble_l(int n, const int *__restrict__ lrp, const int *__restrict__ lci,
+                                const double *__restrict__ lv, int *__restrict__ Lrp, int *__restrict__ Lci,
+                                double *__restrict__ Lv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    Lrp[i] = lrp[i] + i;
+    if (i == n) return;
+    int o = lrp[i] + i;
+    for (int q = lrp[i]; q < lrp[i + 1]; ++q, ++o) {
+        Lci[o] = lci[q];
+        Lv[o] = lv[q];
+    }
+    Lci[o] = i;
+    Lv[o] = 1.0;
+}
+
 }  // namespace
 
-void parilu_device(Allocator *a, const HostCsr &E, int sweeps, HostCsr &L, HostCsr &U, hipStream_t s) {
+void parilu_device(Allocator *a, const DevCsr &E, int sweeps, DevCsr &L, DevCsr &U, hipStream_t s) {
     if (sweeps < 0) fail(SAIT_E_INVALID, "ParILU: sweeps must be >= 0");
-    const int64_t n = E.n;
-    // host: split the pattern, check the diagonal
-    std::vector<int32_t> lrp(n + 1, 0), urp(n + 1, 0), lci, uci, lrow, urow;
-    std::vector<double> la, ua;
-    lci.reserve(E.nnz());
-    uci.reserve(E.nnz());
-    for (int64_t i = 0; i < n; ++i) {
-        bool diag = false;
-        for (int32_t q = E.rp[i]; q < E.rp[i + 1]; ++q) {
-            const int32_t j = E.ci[q];
-            if (j < i) {
-                lci.push_back(j);
-                la.push_back(E.v[q]);
-                lrow.push_back((int32_t)i);
-            } else {
-                if (j == i) diag = E.v[q] != 0.0;
-                uci.push_back(j);
-                ua.push_back(E.v[q]);
-                urow.push_back((int32_t)i);
-            }
-        }
-        if (!diag) fail(SAIT_E_ZERO_PIVOT, "ParILU: zero or missing diagonal entry");
-        lrp[i + 1] = (int32_t)lci.size();
-        urp[i + 1] = (int32_t)uci.size();
-    }
-    const int64_t nl = (int64_t)lci.size(), nu = (int64_t)uci.size();
-    if (nl + nu > INT32_MAX) fail(SAIT_E_INVALID, "ParILU: more than 2^31-1 entries");
-    auto up = [&](DevBuf &d, const void *src, size_t bytes) {
-        d.alloc(a, std::max<size_t>(bytes, 16));
-        if (bytes) SAIT_HIP(hipMemcpyAsync(d.as<void>(), src, bytes, hipMemcpyHostToDevice, s));
-    };
-    DevBuf dlrp, dlci, dlrow, dla, durp, duci, durow, dua, bl[2], bu[2], err;
-    up(dlrp, lrp.data(), (n + 1) * sizeof(int32_t));
-    up(dlci, lci.data(), nl * sizeof(int32_t));
-    up(dlrow, lrow.data(), nl * sizeof(int32_t));
-    up(dla, la.data(), nl * sizeof(double));
-    up(durp, urp.data(), (n + 1) * sizeof(int32_t));
-    up(duci, uci.data(), nu * sizeof(int32_t));
-    up(durow, urow.data(), nu * sizeof(int32_t));
-    up(dua, ua.data(), nu * sizeof(double));
-    for (int b = 0; b < 2; ++b) {
-        bl[b].alloc(a, std::max<size_t>(nl * sizeof(double), 16));
-        bu[b].alloc(a, std::max<size_t>(nu * sizeof(double), 16));
-    }
+    const int n = (int)E.n;
+    const int rgrid = std::max(1, (n + 256) / 256);
+    DevBuf lcnt, ucnt, lptr, uptr, err;
+    lcnt.alloc(a, (size_t)std::max(n, 1) * sizeof(int64_t));
+    ucnt.alloc(a, (size_t)std::max(n, 1) * sizeof(int64_t));
+    lptr.alloc(a, (size_t)(n + 1) * sizeof(int64_t));
+    uptr.alloc(a, (size_t)(n + 1) * sizeof(int64_t));
     err.alloc(a, sizeof(int));
     SAIT_HIP(hipMemsetAsync(err.as<void>(), 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_pl_count, dim3(rgrid), dim3(256), 0, s, n, E.rp.as<int>(), E.ci.as<int>(), E.v.as<double>(),
+                       lcnt.as<int64_t>(), ucnt.as<int64_t>(), err.as<int>());
+    SAIT_LAUNCH_CHECK();
+    scan_exclusive_i64(a, lcnt.as<int64_t>(), lptr.as<int64_t>(), n, s);
+    scan_exclusive_i64(a, ucnt.as<int64_t>(), uptr.as<int64_t>(), n, s);
+    int64_t nl = 0, nu = 0;
+    int herr = 0;
+    SAIT_HIP(hipMemcpyAsync(&nl, lptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SAIT_HIP(hipMemcpyAsync(&nu, uptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SAIT_HIP(hipMemcpyAsync(&herr, err.as<void>(), sizeof(int), hipMemcpyDeviceToHost, s));
+    SAIT_HIP(hipStreamSynchronize(s));
+    if (herr) fail(SAIT_E_ZERO_PIVOT, "ParILU: zero or missing diagonal entry");
+    if (nl + nu + n > INT32_MAX) fail(SAIT_E_INVALID, "ParILU: more than 2^31-1 entries");
+    DevBuf dlrp, dlci, dlrow, dla, durow, bl[2], bu[2];
+    U.n = n;
+    U.nnz = nu;
+    U.precision = SAIT_F64;
+    dlrp.alloc(a, (size_t)(n + 1) * sizeof(int));
+    U.rp.alloc(a, (size_t)(n + 1) * sizeof(int));
+    dlci.alloc(a, (size_t)std::max<int64_t>(nl, 1) * sizeof(int));
+    dlrow.alloc(a, (size_t)std::max<int64_t>(nl, 1) * sizeof(int));
+    dla.alloc(a, (size_t)std::max<int64_t>(nl, 1) * sizeof(double));
+    U.ci.alloc(a, (size_t)std::max<int64_t>(nu, 1) * sizeof(int));
+    durow.alloc(a, (size_t)std::max<int64_t>(nu, 1) * sizeof(int));
+    DevBuf dua;
+    dua.alloc(a, (size_t)std::max<int64_t>(nu, 1) * sizeof(double));
+    for (int b = 0; b < 2; ++b) {
+        bl[b].alloc(a, (size_t)std::max<int64_t>(nl, 1) * sizeof(double));
+        bu[b].alloc(a, (size_t)std::max<int64_t>(nu, 1) * sizeof(double));
+    }
+    hipLaunchKernelGGL(k_pl_split, dim3(rgrid), dim3(256), 0, s, n, E.rp.as<int>(), E.ci.as<int>(), E.v.as<double>(),
+                       lptr.as<int64_t>(), uptr.as<int64_t>(), dlrp.as<int>(), U.rp.as<int>(), dlci.as<int>(),
+                       dla.as<double>(), dlrow.as<int>(), U.ci.as<int>(), dua.as<double>(), durow.as<int>());
+    SAIT_LAUNCH_CHECK();
     Pattern p;
     p.lrp = dlrp.as<int>();
     p.lci = dlci.as<int>();
     p.lrow = dlrow.as<int>();
     p.la = dla.as<double>();
-    p.urp = durp.as<int>();
-    p.uci = duci.as<int>();
+    p.urp = U.rp.as<int>();
+    p.uci = U.ci.as<int>();
     p.urow = durow.as<int>();
     p.ua = dua.as<double>();
     p.nl = (int)nl;
@@ -167,32 +230,22 @@ void parilu_device(Allocator *a, const HostCsr &E, int sweeps, HostCsr &L, HostC
         SAIT_LAUNCH_CHECK();
         cur ^= 1;
     }
-    std::vector<double> lv(nl), uv(nu);
-    if (nl) SAIT_HIP(hipMemcpyAsync(lv.data(), bl[cur].as<void>(), nl * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (nu) SAIT_HIP(hipMemcpyAsync(uv.data(), bu[cur].as<void>(), nu * sizeof(double), hipMemcpyDeviceToHost, s));
-    int herr = 0;
+    // U takes the final value buffer; L gets its unit diagonal
+    U.v = std::move(bu[cur]);
+    U.vs.reset();
+    L.n = n;
+    L.nnz = nl + n;
+    L.precision = SAIT_F64;
+    L.vs.reset();
+    L.rp.alloc(a, (size_t)(n + 1) * sizeof(int));
+    L.ci.alloc(a, (size_t)std::max<int64_t>(nl + n, 1) * sizeof(int));
+    L.v.alloc(a, (size_t)std::max<int64_t>(nl + n, 1) * sizeof(double));
+    hipLaunchKernelGGL(k_pl_assemble_l, dim3(rgrid), dim3(256), 0, s, n, dlrp.as<int>(), dlci.as<int>(),
+                       bl[cur].as<double>(), L.rp.as<int>(), L.ci.as<int>(), L.v.as<double>());
+    SAIT_LAUNCH_CHECK();
     SAIT_HIP(hipMemcpyAsync(&herr, err.as<void>(), sizeof(int), hipMemcpyDeviceToHost, s));
     SAIT_HIP(hipStreamSynchronize(s));
     if (herr) fail(SAIT_E_NONFINITE, "ParILU: the sweeps produced a non-finite factor entry");
-    // L with its unit diagonal (after the row's strictly lower entries), U
-    L = HostCsr{};
-    U = HostCsr{};
-    L.n = U.n = n;
-    L.rp.assign(n + 1, 0);
-    L.ci.reserve(nl + n);
-    L.v.reserve(nl + n);
-    for (int64_t i = 0; i < n; ++i) {
-        for (int32_t e = lrp[i]; e < lrp[i + 1]; ++e) {
-            L.ci.push_back(lci[e]);
-            L.v.push_back(lv[e]);
-        }
-        L.ci.push_back((int32_t)i);
-        L.v.push_back(1.0);
-        L.rp[i + 1] = (int32_t)L.ci.size();
-    }
-    U.rp = std::move(urp);
-    U.ci = std::move(uci);
-    U.v = std::move(uv);
 }
 
 }  // namespace sait

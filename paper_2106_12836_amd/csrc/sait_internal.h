@@ -116,10 +116,6 @@ void host_ilut(const HostCsr &A, double tau, int fill, HostCsr &L, HostCsr &U);
 void host_iluk(const HostCsr &A, int level, HostCsr &L, HostCsr &U);
 // A on its level-p pattern: A's values, explicit zeros at the kept fill.
 void host_iluk_pattern(const HostCsr &A, int level, HostCsr &E);
-// Fine-grained parallel ILU on the pattern of E: `sweeps` synchronous
-// fixed-point sweeps on the device (k_parilu.hip); L unit lower with its
-// diagonal stored, U upper.
-void parilu_device(Allocator *a, const HostCsr &E, int sweeps, HostCsr &L, HostCsr &U, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // SpGEMM construction of the SAIT factors (k_spgemm.hip)
@@ -137,6 +133,10 @@ struct SaitParams {
 void upload_csr(Allocator *a, const HostCsr &h, DevCsr &d, hipStream_t s);
 // Download a device CSR (FP64 values).
 void download_csr(const DevCsr &d, HostCsr &h, hipStream_t s);
+// Fine-grained parallel ILU on the pattern of the device matrix E:
+// `sweeps` synchronous fixed-point sweeps (k_parilu.hip); L unit lower with
+// its diagonal stored, U upper, both on the device.
+void parilu_device(Allocator *a, const DevCsr &E, int sweeps, DevCsr &L, DevCsr &U, hipStream_t s);
 // Build M ~ T^-1 for a device-resident triangular T.
 void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCsr &M, hipStream_t s);
 // One unscaled pass M_next = drop(T~ M_prev + I), or drop(M_prev T~ + I)
