@@ -56,6 +56,7 @@ def lib():
         L.or_iluk.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_iluk_pattern.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d]
         L.or_parilu.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
+        L.or_paric.argtypes = [I64, _i32p, _i32p, _f64p, C.c_int, pp_i, pp_i, pp_d, pp_i, pp_i, pp_d]
         L.or_lower_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_upper_solve.argtypes = [I64, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.or_sait_step.argtypes = [I64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, D, C.c_int, C.c_int, pp_i, pp_i,
@@ -168,6 +169,18 @@ def parilu(A: Csr, sweeps: int, level: int = 0):
     Lo, Uo = _out3(), _out3()
     st = lib().or_parilu(E.n, rp, ci, v, int(sweeps), *(C.byref(x) for x in Lo), *(C.byref(x) for x in Uo))
     _check(st, "parilu")
+    return _take(E.n, *Lo), _take(E.n, *Uo)
+
+
+def paric(A: Csr, sweeps: int, level: int = 0):
+    """Symmetric (incomplete Cholesky) form of the synchronous fine-grained
+    parallel ILU on the level-`level` pattern of a symmetric A (its upper
+    triangle is read).  Returns (L, U) with l_ji = u_ij / u_ii."""
+    E = A if level == 0 else iluk_pattern(A, level)
+    keep, (rp, ci, v) = _csr_args(E)
+    Lo, Uo = _out3(), _out3()
+    st = lib().or_paric(E.n, rp, ci, v, int(sweeps), *(C.byref(x) for x in Lo), *(C.byref(x) for x in Uo))
+    _check(st, "paric")
     return _take(E.n, *Lo), _take(E.n, *Uo)
 
 

@@ -469,6 +469,105 @@ out:
     return st;
 }
 
+/*
+ * Symmetric (incomplete Cholesky) form of the same iteration, for a
+ * symmetric A (only its upper triangle is read): the unknowns are the
+ * u_ij, i <= j, on the upper pattern, and l_ki = u_ik / u_ii throughout, so
+ *     u_ij = a_ij - sum_{k < i} (u_ki / u_kk) u_kj
+ * over k with (k,i) and (k,j) in the pattern.  Every sweep recomputes all
+ * u_ij from the previous sweep's U (each product formed as
+ * fl(fl(u_ki / u_kk) * u_kj), subtracted in increasing k); the start is
+ * u_ij = a_ij.  L is taken from the final U (l_ji = u_ij / u_ii, unit
+ * diagonal), so U = D L^T up to that division's rounding after any number
+ * of sweeps.
+ */
+int or_paric(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int sweeps,
+             int32_t **Lrp, int32_t **Lci, double **Lv,
+             int32_t **Urp, int32_t **Uci, double **Uv) {
+    if (sweeps < 0) return OR_E_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t nu = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int diag = 0;
+        for (int64_t q = rp[i]; q < rp[i + 1]; q++) {
+            if (ci[q] >= i) nu++;
+            if (ci[q] == i) diag = (v[q] != 0.0);
+        }
+        if (!diag) return OR_E_ZERO_PIVOT;
+    }
+    int32_t *urp = (int32_t *)malloc(sizeof(int32_t) * (nn + 1));
+    int32_t *uci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nu + 1));
+    double *ua = (double *)malloc(sizeof(double) * (size_t)(nu + 1));
+    double *u0 = (double *)malloc(sizeof(double) * (size_t)(nu + 1));
+    double *u1 = (double *)malloc(sizeof(double) * (size_t)(nu + 1));
+    /* column lists of U (rows k < i holding column i), as (k, position) */
+    int32_t *ccnt = (int32_t *)calloc(nn + 1, sizeof(int32_t));
+    int32_t *crow = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nu + 1));
+    int64_t *cpos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nu + 1));
+    int32_t *cfill = (int32_t *)calloc(nn, sizeof(int32_t));
+    int st = OR_OK;
+    if (!urp || !uci || !ua || !u0 || !u1 || !ccnt || !crow || !cpos || !cfill) { st = OR_E_NOMEM; goto out; }
+    {
+        int64_t b = 0;
+        urp[0] = 0;
+        for (int64_t i = 0; i < n; i++) {
+            for (int64_t q = rp[i]; q < rp[i + 1]; q++)
+                if (ci[q] >= i) { uci[b] = ci[q]; ua[b] = v[q]; b++; }
+            urp[i + 1] = (int32_t)b;
+        }
+    }
+    /* strictly upper entries (k, i), k < i, grouped by column i, rows ascending */
+    for (int64_t k = 0; k < n; k++)
+        for (int64_t e = urp[k] + 1; e < urp[k + 1]; e++) ccnt[uci[e] + 1]++;
+    for (int64_t i = 0; i < n; i++) ccnt[i + 1] += ccnt[i];
+    for (int64_t k = 0; k < n; k++)
+        for (int64_t e = urp[k] + 1; e < urp[k + 1]; e++) {
+            int32_t i = uci[e];
+            int64_t o = ccnt[i] + cfill[i]++;
+            crow[o] = (int32_t)k;
+            cpos[o] = e;
+        }
+    for (int64_t e = 0; e < nu; e++) u0[e] = ua[e];
+    for (int s = 0; s < sweeps; s++) {
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t e = urp[i]; e < urp[i + 1]; e++) {
+                int32_t j = uci[e];
+                double t = ua[e];
+                for (int64_t q = ccnt[i]; q < ccnt[i + 1]; q++) {
+                    int32_t k = crow[q];
+                    int64_t f = find_col(uci, urp[k], urp[k + 1], j);
+                    if (f >= 0) t = t - (u0[cpos[q]] / u0[urp[k]]) * u0[f];
+                }
+                u1[e] = t;
+            }
+        double *tu = u0; u0 = u1; u1 = tu;
+    }
+    for (int64_t e = 0; e < nu; e++) if (!isfinite(u0[e])) st = OR_E_NONFINITE;
+    if (st != OR_OK) goto out;
+    {
+        or_builder Lb, Ub;
+        st = bld_init(&Lb, n, nu);
+        if (st == OR_OK) st = bld_init(&Ub, n, nu);
+        if (st != OR_OK) goto out;
+        for (int64_t i = 0; i < n; i++) {
+            for (int64_t q = ccnt[i]; q < ccnt[i + 1]; q++) {
+                int32_t k = crow[q];
+                bld_push(&Lb, k, u0[cpos[q]] / u0[urp[k]]);   /* l_ik = u_ki / u_kk */
+            }
+            bld_push(&Lb, (int32_t)i, 1.0);
+            bld_end_row(&Lb, i);
+            for (int64_t e = urp[i]; e < urp[i + 1]; e++) bld_push(&Ub, uci[e], u0[e]);
+            bld_end_row(&Ub, i);
+        }
+        bld_give(&Lb, Lrp, Lci, Lv);
+        bld_give(&Ub, Urp, Uci, Uv);
+    }
+out:
+    free(urp); free(uci); free(ua); free(u0); free(u1);
+    free(ccnt); free(crow); free(cpos); free(cfill);
+    return st;
+}
+
 /* ------------------------------------------------------------------ */
 /* ILUT(tau, p): Saad Alg. 10.6 (dual threshold).                       */
 /* ------------------------------------------------------------------ */

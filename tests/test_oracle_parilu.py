@@ -92,3 +92,56 @@ def test_zero_diagonal_rejected():
     A = Csr(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([0.0, 1.0, 1.0, 2.0]))
     with pytest.raises(Exception):
         oracle.parilu(A, 2)
+
+
+# ---- symmetric (incomplete Cholesky) form ------------------------------------
+
+def _sym_rdd(n, seed):
+    B = random_diag_dominant(n, 5, band=30, seed=seed).to_scipy()
+    S = (B + B.T).tocsr()
+    S.setdiag(np.abs(S).sum(axis=1).A1 + 1.0)
+    S.sort_indices()
+    return Csr.from_scipy(S)
+
+
+@pytest.mark.parametrize("maker", [lambda: poisson3d(6), lambda: poisson2d(12), lambda: _sym_rdd(200, 3)])
+def test_paric_converges_to_ilu0(maker):
+    A = maker()
+    L, U = oracle.paric(A, 200)
+    L0, U0 = oracle.ilu0(A)
+    assert np.array_equal(L.ci, L0.ci) and np.array_equal(U.ci, U0.ci)
+    np.testing.assert_allclose(U.v, U0.v, rtol=1e-13, atol=1e-14 * np.abs(U0.v).max())
+    np.testing.assert_allclose(L.v, L0.v, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("s", [0, 1, 3])
+def test_paric_symmetric_after_every_sweep(s):
+    A = _sym_rdd(150, 4)
+    L, U = oracle.paric(A, s)
+    Ld, Ud = L.to_scipy().toarray(), U.to_scipy().toarray()
+    d = np.diag(Ud)
+    # l_ji = fl(u_ij / u_ii): the unit-lower factor is D^-1 U transposed
+    np.testing.assert_allclose(Ld.T, np.triu(Ud, 1) / d[:, None] + np.eye(A.n), rtol=1e-15, atol=0)
+
+
+def test_paric_zero_sweeps_and_tridiagonal_one_sweep():
+    A, lo, dg, up = _tridiag(30, 8)
+    Ad = A.to_scipy().toarray()
+    S = np.triu(Ad) + np.triu(Ad, 1).T            # the symmetric matrix of A's upper triangle
+    L, U = oracle.paric(Csr.from_scipy(sp.csr_matrix(S)), 0)
+    np.testing.assert_array_equal(U.to_scipy().toarray(), np.triu(S))
+    L1, U1 = oracle.paric(Csr.from_scipy(sp.csr_matrix(S)), 1)
+    want = dg.copy()
+    want[1:] = dg[1:] - (up / dg[:-1]) * up       # u_ii = a_ii - (u_(i-1,i) / u_(i-1,i-1)) u_(i-1,i)
+    np.testing.assert_allclose(np.diag(U1.to_scipy().toarray()), want, rtol=1e-15)
+
+
+def test_paric_gives_symmetric_sait_preconditioner():
+    # with the upper factor right-multiplied, the SAIT pair of the symmetric
+    # factors is symmetric up to rounding even after a single sweep
+    A = poisson3d(7)
+    L, U = oracle.paric(A, 1)
+    ML, MU = oracle.sait_factors(L, U, 4, tau=0.02)
+    P = (MU.to_scipy() @ ML.to_scipy()).toarray()
+    assert np.abs(P - P.T).max() <= 1e-13 * np.abs(P).max()
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
