@@ -383,7 +383,8 @@ def parilu_experiment(torch, dev):
     and PCG iterations to 1e-10 (f ~ U[0, 1), seed 0) with that SAIT
     preconditioner.  GMRES takes any preconditioner; PCG needs a symmetric
     one, which intermediate synchronous sweeps do not give (each sweep
-    divides by the previous sweep's pivots)."""
+    divides by the previous sweep's pivots); the symmetric (incomplete
+    Cholesky) form, 1, 2 and 3 sweeps, does."""
     from paper_2106_12836_amd import SaitPreconditioner
     from workloads import poisson3d
 
@@ -414,6 +415,8 @@ def parilu_experiment(torch, dev):
                         "(seed 0)", host_ilu0=run())
     for sw in (1, 2, 3, 5):
         out[f"parilu_{sw}"] = run(ilu_kind="parilu", ilu_level=0, parilu_sweeps=sw)
+    for sw in (1, 2, 3):
+        out[f"paric_{sw}"] = run(ilu_kind="paric", ilu_level=0, parilu_sweeps=sw)
     print(f"[bench] parilu: {out}", file=sys.stderr, flush=True)
     return out
 

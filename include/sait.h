@@ -60,8 +60,13 @@ enum {
  * pattern is formed on the host, the factors on the device by synchronous
  * sweeps u_ij = a_ij - sum_{k<i} l_ik u_kj, l_ij = (a_ij - sum_{k<j} l_ik u_kj)
  * / u_jj over the pattern; enough sweeps give the ILU factors of that
- * pattern exactly. */
-enum { SAIT_ILU0 = 0, SAIT_ILUT = 1, SAIT_ILUK = 2, SAIT_PARILU = 3 };
+ * pattern exactly.  SAIT_PARIC is its symmetric (incomplete Cholesky) form
+ * for a symmetric A: only u_ij (i <= j) are iterated, u_ij = a_ij -
+ * sum_{k<i} (u_ki / u_kk) u_kj, and l_ji = u_ij / u_ii, so L and U stay
+ * symmetric after every sweep (as PCG needs); the pattern must be
+ * structurally symmetric (SAIT_E_INVALID otherwise) and the upper triangle
+ * of A is read. */
+enum { SAIT_ILU0 = 0, SAIT_ILUT = 1, SAIT_ILUK = 2, SAIT_PARILU = 3, SAIT_PARIC = 4 };
 
 /* Storage precision of M_L, M_U values (accumulation is FP64 for SAIT_F64,
  * binary32 otherwise). */
@@ -81,8 +86,9 @@ typedef struct {
 
 /* Build options (sait_default_build_opts fills the defaults in brackets). */
 typedef struct {
-    int ilu_kind;        /* SAIT_ILU0 [default], SAIT_ILUT, SAIT_ILUK (levels of fill, Sec. 4), or SAIT_PARILU
-                            (fine-grained parallel ILU on the device, on the level-ilu_level pattern) */
+    int ilu_kind;        /* SAIT_ILU0 [default], SAIT_ILUT, SAIT_ILUK (levels of fill, Sec. 4), SAIT_PARILU
+                            (fine-grained parallel ILU on the device, on the level-ilu_level pattern) or
+                            SAIT_PARIC (its symmetric form) */
     double ilut_tau;     /* ILUT drop tolerance, relative to ||a_i,*||_2 [1e-3] */
     int ilut_fill;       /* ILUT: keep at most this many off-diagonals per row in each of L, U [10] */
     int m;               /* number of Horner passes M <- T~ M + I (Alg. 1-3) [3]; for U see upper_side */
@@ -91,9 +97,9 @@ typedef struct {
     int pattern_p;       /* < 0: threshold dropping (SAIT_Thr) [-1];  >= 0: SAIT_Pat(p, m) (Alg. 3) */
     int precision;       /* SAIT_F64 [default], SAIT_F32 or SAIT_BF16 storage of M_L, M_U */
     int build_transpose; /* also build A^T, M_L^T, M_U^T for transpose solves / gradients [0] */
-    int ilu_level;       /* SAIT_ILUK, SAIT_PARILU: keep fill of level <= ilu_level (1: the paper's level-1 ILU) [1] */
+    int ilu_level;       /* SAIT_ILUK, SAIT_PARILU, SAIT_PARIC: keep fill of level <= ilu_level (1: level-1 ILU) [1] */
     int upper_side;      /* side of T~ in the passes that build M_U: SAIT_SIDE_RIGHT [default] or SAIT_SIDE_LEFT */
-    int parilu_sweeps;   /* SAIT_PARILU: synchronous fixed-point sweeps from l_ij = a_ij / a_jj, u_ij = a_ij [3] */
+    int parilu_sweeps;   /* SAIT_PARILU, SAIT_PARIC: synchronous sweeps from l_ij = a_ij / a_jj, u_ij = a_ij [3] */
 } sait_build_opts;
 
 /* Side of T~ in a Horner pass.  SAIT_SIDE_LEFT: M <- drop(T~ M + I), Alg. 1

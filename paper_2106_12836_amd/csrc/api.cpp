@@ -239,12 +239,12 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         sait_build_opts opts;
         sait_default_build_opts(&opts);
         if (o) opts = *o;
-        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT && opts.ilu_kind != SAIT_ILUK &&
-            opts.ilu_kind != SAIT_PARILU)
+        const bool device_ilu = opts.ilu_kind == SAIT_PARILU || opts.ilu_kind == SAIT_PARIC;
+        if (opts.ilu_kind != SAIT_ILU0 && opts.ilu_kind != SAIT_ILUT && opts.ilu_kind != SAIT_ILUK && !device_ilu)
             fail(SAIT_E_INVALID, "unknown ilu_kind");
-        if ((opts.ilu_kind == SAIT_ILUK || opts.ilu_kind == SAIT_PARILU) && opts.ilu_level < 0)
+        if ((opts.ilu_kind == SAIT_ILUK || device_ilu) && opts.ilu_level < 0)
             fail(SAIT_E_INVALID, "ilu_level must be >= 0");
-        if (opts.ilu_kind == SAIT_PARILU && opts.parilu_sweeps < 0) fail(SAIT_E_INVALID, "parilu_sweeps must be >= 0");
+        if (device_ilu && opts.parilu_sweeps < 0) fail(SAIT_E_INVALID, "parilu_sweeps must be >= 0");
         if (opts.upper_side != SAIT_SIDE_LEFT && opts.upper_side != SAIT_SIDE_RIGHT)
             fail(SAIT_E_INVALID, "upper_side must be SAIT_SIDE_LEFT or SAIT_SIDE_RIGHT");
         if (opts.precision != SAIT_F64 && opts.precision != SAIT_F32 && opts.precision != SAIT_BF16)
@@ -289,15 +289,16 @@ int sait_build(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const 
         upload_csr(&h->alloc, h->A_h, h->A, s);
         if (opts.ilu_kind == SAIT_ILU0) host_ilu0(h->A_h, h->L_h, h->U_h);
         else if (opts.ilu_kind == SAIT_ILUK) host_iluk(h->A_h, opts.ilu_level, h->L_h, h->U_h);
-        else if (opts.ilu_kind == SAIT_PARILU) {
+        else if (device_ilu) {
+            const bool sym = opts.ilu_kind == SAIT_PARIC;
             if (opts.ilu_level == 0) {
-                parilu_device(&h->alloc, h->A, opts.parilu_sweeps, h->Ld, h->Ud, s);
+                parilu_device(&h->alloc, h->A, opts.parilu_sweeps, sym, h->Ld, h->Ud, s);
             } else {
                 HostCsr E;
                 host_iluk_pattern(h->A_h, opts.ilu_level, E);
                 DevCsr Ed;
                 upload_csr(&h->alloc, E, Ed, s);
-                parilu_device(&h->alloc, Ed, opts.parilu_sweeps, h->Ld, h->Ud, s);
+                parilu_device(&h->alloc, Ed, opts.parilu_sweeps, sym, h->Ld, h->Ud, s);
             }
             h->host_lu = false;
         }

@@ -8,7 +8,12 @@
 // thread each -- from the previous sweep's L and U (double-buffered), the
 // products subtracted in increasing k with separate roundings; the start
 // is l_ij = a_ij / a_jj, u_ij = a_ij.  Deterministic: the factors after s
-// sweeps are the same on every run.  The pattern split and the factors stay
+// sweeps are the same on every run.  For a symmetric A the incomplete
+// Cholesky form keeps only U, with l_ki = u_ik / u_ii throughout:
+//     u_ij = a_ij - sum_{k < i} (u_ki / u_kk) u_kj,
+// so the factors stay symmetric after every sweep (the unsymmetric sweeps
+// divide by the previous sweep's pivots and do not).  The pattern split and
+// the factors stay
 // on the device; a level-k pattern comes from the host's symbolic phase.
 #include <hip/hip_runtime.h>
 
@@ -160,9 +165,63 @@ __global__ void k_pl_assemble_l(int n, const int *__restrict__ lrp, const int *_
     Lv[o] = 1.0;
 }
 
+// Symmetric form: cpos[q] = position of (k, i) in U for the strictly lower
+// entry q = (i, k); err |= 2 when the pattern is not structurally symmetric.
+__global__ void k_pc_map(int nl, const int *__restrict__ lci, const int *__restrict__ lrow,
+                         const int *__restrict__ urp, const int *__restrict__ uci, int *__restrict__ cpos,
+                         int *__restrict__ err) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nl) return;
+    const int k = lci[q], i = lrow[q];
+    const int f = find_col(uci, urp[k], urp[k + 1], i);
+    cpos[q] = f < 0 ? urp[k] : f;
+    if (f < 0) atomicOr(err, 2);
+}
+
+__device__ __forceinline__ double pdiv(double a, double b) { return a / b; }
+
+// One synchronous sweep of the symmetric form over the U entries:
+//   u_ij = a_ij - sum_{k < i} fl(fl(u_ki / u_kk) u_kj),  k ascending.
+__global__ void k_paric_sweep(Pattern p, const int *__restrict__ cpos, const double *__restrict__ u0,
+                              double *__restrict__ u1, int check, int *__restrict__ err) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p.nu) return;
+    const int i = p.urow[e], j = p.uci[e];
+    double acc = p.ua[e];
+    for (int q = p.lrp[i]; q < p.lrp[i + 1]; ++q) {
+        const int k = p.lci[q];
+        const int f = find_col(p.uci, p.urp[k], p.urp[k + 1], j);
+        if (f >= 0) acc = psub(acc, pmul(pdiv(u0[cpos[q]], u0[p.urp[k]]), u0[f]));
+    }
+    u1[e] = acc;
+    if (check && !isfinite(acc)) atomicOr(err, 1);
+}
+
+// L of the symmetric form: l_ik = u_ki / u_kk, then the unit diagonal.
+__global__ void k_pc_assemble_l(int n, const int *__restrict__ lrp, const int *__restrict__ lci,
+                                const int *__restrict__ cpos, const int *__restrict__ urp,
+                                const double *__restrict__ u, int *__restrict__ Lrp, int *__restrict__ Lci,
+                                double *__restrict__ Lv, int *__restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    Lrp[i] = lrp[i] + i;
+    if (i == n) return;
+    int o = lrp[i] + i;
+    for (int q = lrp[i]; q < lrp[i + 1]; ++q, ++o) {
+        const int k = lci[q];
+        const double l = pdiv(u[cpos[q]], u[urp[k]]);
+        Lci[o] = k;
+        Lv[o] = l;
+        if (!isfinite(l)) atomicOr(err, 1);
+    }
+    Lci[o] = i;
+    Lv[o] = 1.0;
+}
+
 }  // namespace
 
-void parilu_device(Allocator *a, const DevCsr &E, int sweeps, DevCsr &L, DevCsr &U, hipStream_t s) {
+void parilu_device(Allocator *a, const DevCsr &E, int sweeps, bool symmetric, DevCsr &L, DevCsr &U,
+                   hipStream_t s) {
     if (sweeps < 0) fail(SAIT_E_INVALID, "ParILU: sweeps must be >= 0");
     const int n = (int)E.n;
     const int rgrid = std::max(1, (n + 256) / 256);
@@ -219,6 +278,45 @@ void parilu_device(Allocator *a, const DevCsr &E, int sweeps, DevCsr &L, DevCsr 
     p.nl = (int)nl;
     p.nu = (int)nu;
     const int grid = (int)std::max<int64_t>(1, (nl + nu + 255) / 256);
+    if (symmetric) {
+        // U only; L follows from the final U
+        DevBuf cpos;
+        cpos.alloc(a, (size_t)std::max<int64_t>(nl, 1) * sizeof(int));
+        hipLaunchKernelGGL(k_pc_map, dim3((int)std::max<int64_t>(1, (nl + 255) / 256)), dim3(256), 0, s, (int)nl,
+                           dlci.as<int>(), dlrow.as<int>(), U.rp.as<int>(), U.ci.as<int>(), cpos.as<int>(),
+                           err.as<int>());
+        SAIT_LAUNCH_CHECK();
+        SAIT_HIP(hipMemcpyAsync(&herr, err.as<void>(), sizeof(int), hipMemcpyDeviceToHost, s));
+        SAIT_HIP(hipStreamSynchronize(s));
+        if (herr & 2) fail(SAIT_E_INVALID, "ParIC: the pattern is not structurally symmetric");
+        SAIT_HIP(hipMemcpyAsync(bu[0].as<void>(), dua.as<void>(), (size_t)nu * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+        const int ugrid = (int)std::max<int64_t>(1, (nu + 255) / 256);
+        int cur = 0;
+        for (int sw = 0; sw < sweeps; ++sw) {
+            hipLaunchKernelGGL(k_paric_sweep, dim3(ugrid), dim3(256), 0, s, p, cpos.as<int>(), bu[cur].as<double>(),
+                               bu[cur ^ 1].as<double>(), (int)(sw + 1 == sweeps), err.as<int>());
+            SAIT_LAUNCH_CHECK();
+            cur ^= 1;
+        }
+        L.n = n;
+        L.nnz = nl + n;
+        L.precision = SAIT_F64;
+        L.vs.reset();
+        L.rp.alloc(a, (size_t)(n + 1) * sizeof(int));
+        L.ci.alloc(a, (size_t)std::max<int64_t>(nl + n, 1) * sizeof(int));
+        L.v.alloc(a, (size_t)std::max<int64_t>(nl + n, 1) * sizeof(double));
+        hipLaunchKernelGGL(k_pc_assemble_l, dim3(rgrid), dim3(256), 0, s, n, dlrp.as<int>(), dlci.as<int>(),
+                           cpos.as<int>(), U.rp.as<int>(), bu[cur].as<double>(), L.rp.as<int>(), L.ci.as<int>(),
+                           L.v.as<double>(), err.as<int>());
+        SAIT_LAUNCH_CHECK();
+        U.v = std::move(bu[cur]);
+        U.vs.reset();
+        SAIT_HIP(hipMemcpyAsync(&herr, err.as<void>(), sizeof(int), hipMemcpyDeviceToHost, s));
+        SAIT_HIP(hipStreamSynchronize(s));
+        if (herr) fail(SAIT_E_NONFINITE, "ParIC: the sweeps produced a non-finite factor entry");
+        return;
+    }
     hipLaunchKernelGGL(k_parilu_start, dim3(grid), dim3(256), 0, s, p, bl[0].as<double>(), bu[0].as<double>(),
                        (int)(sweeps == 0), err.as<int>());
     SAIT_LAUNCH_CHECK();

@@ -135,8 +135,10 @@ void upload_csr(Allocator *a, const HostCsr &h, DevCsr &d, hipStream_t s);
 void download_csr(const DevCsr &d, HostCsr &h, hipStream_t s);
 // Fine-grained parallel ILU on the pattern of the device matrix E:
 // `sweeps` synchronous fixed-point sweeps (k_parilu.hip); L unit lower with
-// its diagonal stored, U upper, both on the device.
-void parilu_device(Allocator *a, const DevCsr &E, int sweeps, DevCsr &L, DevCsr &U, hipStream_t s);
+// its diagonal stored, U upper, both on the device.  symmetric: the
+// incomplete Cholesky form (structurally symmetric pattern, upper triangle
+// of E read, l_ki = u_ik / u_ii).
+void parilu_device(Allocator *a, const DevCsr &E, int sweeps, bool symmetric, DevCsr &L, DevCsr &U, hipStream_t s);
 // Build M ~ T^-1 for a device-resident triangular T.
 void build_sait_factor(Allocator *a, const DevCsr &T, const SaitParams &p, DevCsr &M, hipStream_t s);
 // One unscaled pass M_next = drop(T~ M_prev + I), or drop(M_prev T~ + I)

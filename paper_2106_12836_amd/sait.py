@@ -21,7 +21,7 @@ _LIB = None
 
 SAIT_OK, SAIT_NOT_CONVERGED, SAIT_BREAKDOWN = 0, 1, 2
 SAIT_E_INVALID, SAIT_E_ZERO_PIVOT, SAIT_E_NONFINITE, SAIT_E_NOMEM, SAIT_E_DEVICE = -1, -2, -3, -4, -5
-SAIT_ILU0, SAIT_ILUT, SAIT_ILUK, SAIT_PARILU = 0, 1, 2, 3
+SAIT_ILU0, SAIT_ILUT, SAIT_ILUK, SAIT_PARILU, SAIT_PARIC = 0, 1, 2, 3, 4
 SAIT_SIDE_LEFT, SAIT_SIDE_RIGHT = 0, 1
 SIDES = {"left": SAIT_SIDE_LEFT, "right": SAIT_SIDE_RIGHT}
 SAIT_METHOD_GMRES, SAIT_METHOD_PCG = 0, 1
@@ -161,7 +161,8 @@ def default_build_opts(**kw) -> sait_build_opts:
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
         if k == "ilu_kind" and isinstance(v, str):
-            v = {"ilu0": SAIT_ILU0, "ilut": SAIT_ILUT, "iluk": SAIT_ILUK, "parilu": SAIT_PARILU}[v]
+            v = {"ilu0": SAIT_ILU0, "ilut": SAIT_ILUT, "iluk": SAIT_ILUK, "parilu": SAIT_PARILU,
+                 "paric": SAIT_PARIC}[v]
         if k == "upper_side" and isinstance(v, str):
             v = SIDES[v]
         setattr(o, k, v)

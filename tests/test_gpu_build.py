@@ -13,7 +13,7 @@ import scipy.sparse as sp
 
 import oracle
 from paper_2106_12836_amd import SaitError, SaitPreconditioner, sait_debug_step
-from workloads import (Csr, config, convdiff2d_upwind, poisson2d, poisson3d, random_diag_dominant,
+from workloads import (Csr, aniso2d, config, convdiff2d_upwind, poisson2d, poisson3d, random_diag_dominant,
                        random_triangular)
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +36,8 @@ def _oracle_factors(A, ilu, m, tau, cap=0, p=-1, ilut=(1e-3, 10), level=1, upper
         L, U = oracle.iluk(A, level)
     elif ilu == "parilu":
         L, U = oracle.parilu(A, sweeps, level)
+    elif ilu == "paric":
+        L, U = oracle.paric(A, sweeps, level)
     else:
         L, U = oracle.ilut(A, *ilut)
     if p >= 0:
@@ -59,6 +61,9 @@ CASES = [
                                                                                   ilu_level=0, parilu_sweeps=0)),
     ("convdiff-parilu-l1", lambda: convdiff2d_upwind(30, 10.0), dict(m=4, tau=1e-3, ilu_kind="parilu", ilu_level=1,
                                                                       parilu_sweeps=2)),
+    ("p3d-paric1", lambda: poisson3d(9), dict(m=4, tau=1e-2, ilu_kind="paric", ilu_level=0, parilu_sweeps=1)),
+    ("p2d-paric-l1", lambda: poisson2d(24), dict(m=3, tau=1e-2, ilu_kind="paric", ilu_level=1, parilu_sweeps=2)),
+    ("aniso-paric0", lambda: aniso2d(30, 0.05), dict(m=3, tau=1e-2, ilu_kind="paric", ilu_level=0, parilu_sweeps=0)),
     ("cap5", lambda: poisson3d(7), dict(m=4, tau=0.0, max_nnz_row=5)),
     ("rdd-cap6", lambda: random_diag_dominant(1200, 8, band=90, seed=8), dict(m=3, tau=1e-3, max_nnz_row=6)),
     ("pat2", lambda: poisson3d(8), dict(m=3, tau=0.0, pattern_p=2)),
@@ -234,6 +239,13 @@ def test_parilu_reaches_the_ilu_factors(level):
             np.testing.assert_array_equal(v, ref.v)
     finally:
         pre.close()
+
+
+def test_paric_needs_a_symmetric_pattern():
+    print("[test_paric_needs_a_symmetric_pattern]", flush=True)
+    with pytest.raises(SaitError) as e:
+        SaitPreconditioner(random_diag_dominant(300, 6, band=40, seed=13), ilu_kind="paric", ilu_level=0)
+    assert e.value.status == -1
 
 
 def test_parilu_errors():
