@@ -73,6 +73,10 @@ CASES = [
                                                                                          upper_side="left")),
     ("m0", lambda: poisson2d(9), dict(m=0, tau=0.1)),
     ("n1", lambda: Csr(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])), dict(m=2, tau=0.1)),
+    ("n1-parilu", lambda: Csr(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])),
+     dict(m=2, tau=0.1, ilu_kind="parilu", ilu_level=0, parilu_sweeps=2)),
+    ("n1-paric", lambda: Csr(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([3.0])),
+     dict(m=2, tau=0.1, ilu_kind="paric", ilu_level=0, parilu_sweeps=2)),
 ]
 
 
@@ -262,3 +266,20 @@ def test_parilu_errors():
     with pytest.raises(SaitError) as e:
         SaitPreconditioner(B, ilu_kind="parilu", ilu_level=0, parilu_sweeps=2)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("kind,sweeps", [("parilu", 3), ("paric", 1)])
+def test_device_ilu_full_size(kind, sweeps):
+    # the paper's 100^3 matrix (6.94 M entries): device factors bit for bit
+    print(f"[test_device_ilu_full_size] {kind} sweeps={sweeps}", flush=True)
+    A = poisson3d(100)
+    L, U = (oracle.parilu if kind == "parilu" else oracle.paric)(A, sweeps)
+    pre = SaitPreconditioner(A, m=0, tau=0.0, ilu_kind=kind, ilu_level=0, parilu_sweeps=sweeps)
+    try:
+        for which, ref in (("L", L), ("U", U)):
+            rp, ci, v = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v, ref.v)
+    finally:
+        pre.close()

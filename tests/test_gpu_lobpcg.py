@@ -192,3 +192,26 @@ def test_lobpcg_paper_size(level):
         _check_block(pre, lam, X, 1e-8)
     finally:
         pre.close()
+
+
+def test_lobpcg_smallest_problem():
+    # n = 3k (k = 5): the trial space [X, W, P] is the whole space from the
+    # second step on, so the Ritz values are exact
+    print("[test_lobpcg_smallest_problem]", flush=True)
+    import scipy.linalg as sla
+    import scipy.sparse as sp
+    from workloads import Csr
+    torch = _torch()
+    B = sp.random(15, 15, density=0.4, random_state=3).toarray()
+    Ad = B @ B.T + 15 * np.eye(15)
+    A = Csr.from_scipy(sp.csr_matrix(Ad))
+    pre = SaitPreconditioner(A, m=2, tau=0.0)
+    try:
+        pre.set_preconditioner("none")
+        lam, X, info = pre.lobpcg(torch.tensor(_start(15, 5, 4), device="cuda:0"), tol=1e-12, maxit=20)
+        ref = oracle.lobpcg(A, _start(15, 5, 4), None, tol=1e-12, maxit=20)
+        assert info["status"] == 0 and info["iterations"] <= 3, info
+        np.testing.assert_allclose(lam, sla.eigvalsh(Ad)[:5], rtol=1e-12)
+        np.testing.assert_allclose(lam, ref["lam"], rtol=1e-12)
+    finally:
+        pre.close()
