@@ -102,12 +102,19 @@ __global__ __launch_bounds__(kGramThreads) void k_gram(GramArgs a, double *__res
     }
 }
 
-// out[e] = sum over p < nparts of part[p * width + e], one workgroup per
-// entry, summed in a fixed tree order (deterministic).
-__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, int nparts, int width,
-                                                      double *__restrict__ out) {
+// Both reductions of a step in one launch: workgroup e < wa writes
+// oa[e] = sum over p < na of pa[p * wa + e] (the Gram tiles), workgroup
+// wa + e writes ob[e] = sum over p < nb of pb[p * wb + e] (the residual
+// norms of the previous update); each sum in a fixed tree order
+// (deterministic).
+__global__ __launch_bounds__(256) void k_sum_two(const double *__restrict__ pa, int na, int wa,
+                                                 double *__restrict__ oa, const double *__restrict__ pb, int nb,
+                                                 int wb, double *__restrict__ ob) {
     __shared__ double sh[256];
-    const int e = blockIdx.x;
+    const bool first = (int)blockIdx.x < wa;
+    const int e = first ? (int)blockIdx.x : (int)blockIdx.x - wa;
+    const double *part = first ? pa : pb;
+    const int nparts = first ? na : nb, width = first ? wa : wb;
     double t = 0.0;
     for (int p = threadIdx.x; p < nparts; p += 256) t += part[(int64_t)p * width + e];
     sh[threadIdx.x] = t;
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
         if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[e] = sh[0];
+    if (threadIdx.x == 0) (first ? oa : ob)[e] = sh[0];
 }
 
 struct UpdArgs {
@@ -404,7 +411,7 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
     double *dtheta = dcoef + 3 * kMaxBlock * kMaxBlock;
     double *h = B.host;
 
-    auto gram = [&](int nb) {
+    auto gram = [&](int nb, bool with_norms) {
         GramArgs g{};
         g.s[0] = Xi;
         g.s[1] = B.w.as<double>();
@@ -418,8 +425,10 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         g.nb = nb;
         hipLaunchKernelGGL(k_gram, dim3(ggrid), dim3(kGramThreads), 0, s, g, B.gpart.as<double>());
         SAIT_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sum_partials, dim3(2 * kGramTile), dim3(256), 0, s, B.gpart.as<double>(), ggrid,
-                           2 * kGramTile, dG);
+        // the norms of the last update's residual are reduced in the same launch
+        const int wb = with_norms ? k : 0;
+        hipLaunchKernelGGL(k_sum_two, dim3(2 * kGramTile + wb), dim3(256), 0, s, B.gpart.as<double>(), ggrid,
+                           2 * kGramTile, dG, B.upart.as<double>(), ugrid, k, dnorm);
         SAIT_LAUNCH_CHECK();
     };
     auto readback = [&](bool with_norms) {
@@ -452,14 +461,12 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         case 4: launch_update<4>(u, nb, B.upart.as<double>(), ugrid, s); break;
         default: launch_update<5>(u, nb, B.upart.as<double>(), ugrid, s); break;
         }
-        hipLaunchKernelGGL(k_sum_partials, dim3(k), dim3(256), 0, s, B.upart.as<double>(), ugrid, k, dnorm);
-        SAIT_LAUNCH_CHECK();
     };
 
     // Rayleigh-Ritz on span(X0)
     SAIT_HIP(hipMemcpyAsync(Xi, X, blk, hipMemcpyDeviceToDevice, s));
     applyA(Xi, B.ax.as<double>(), s);
-    gram(1);
+    gram(1, false);
     readback(false);
     std::vector<double> theta, coef;
     if (!rayleigh_ritz(k, k, h, h + kGramTile, theta, coef))
@@ -473,7 +480,7 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         applyT(B.r.as<double>(), B.w.as<double>(), s);
         applyA(B.w.as<double>(), B.aw.as<double>(), s);
         const int nb = has_p ? 3 : 2;
-        gram(nb);
+        gram(nb, true);
         readback(true);
         relres = 0.0;
         for (int j = 0; j < k; ++j)
