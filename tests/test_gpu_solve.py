@@ -345,3 +345,82 @@ def test_autograd_c5_full_size():
         dan = gA @ xi + gb @ eta
         print(f"[test_autograd_c5_full_size] direction {d}: fd {dfd:.10e} adjoint {dan:.10e}", flush=True)
         assert abs(dfd - dan) <= 1e-6 * max(abs(dfd), abs(dan)), (d, dfd, dan)
+
+
+def test_c3_full_size():
+    # the headline workload at full size (3D Poisson 128^3, n = 2,097,152,
+    # ILU(0) + SAIT_Thr(1e-3, 3)): factors bit for bit, the FP64 apply in the
+    # autotuned launch shape the bench times bit for bit (sliced ELL) or
+    # within the wavefront bound, and FGMRES(40) to a 1e-10 true residual in
+    # the oracle's iteration count; FP32 / BF16 factors within 2 steps of it
+    print("[test_c3_full_size] building", flush=True)
+    c = config("c3")
+    A = c["A"]
+    L, U = oracle.ilu0(A)
+    ML, MU = oracle.sait_factors(L, U, c["m"], tau=c["tau"])
+    pre = SaitPreconditioner(A, m=c["m"], tau=c["tau"])
+    try:
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, _ = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v, ref.v)
+        lanes = pre.autotune()
+        print(f"[test_c3_full_size] apply shapes {lanes}", flush=True)
+        r = uniform_vector(A.n, 11)
+        z = pre.apply(_t(r)).cpu().numpy()
+        zr = oracle.apply(ML, MU, r)
+        if all(x in (-64, -65, -8, -16) for x in lanes):
+            np.testing.assert_array_equal(z, zr)
+        else:
+            assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+        print("[test_c3_full_size] solving", flush=True)
+        b = _t(c["b"])
+        x, (info,) = pre.solve(b, restart=c["restart"], rtol=c["rtol"], flexible=True)
+        ref = oracle.gmres(A, c["b"], ("sait64", ML, MU), restart=c["restart"], rtol=c["rtol"], flexible=True)
+        assert info.status == 0 and info.true_relres <= c["rtol"], info
+        assert abs(info.iterations - ref["iters"]) <= 1, (info.iterations, ref["iters"])
+    finally:
+        pre.close()
+    for prec in ("f32", "bf16"):
+        p2 = SaitPreconditioner(A, m=c["m"], tau=c["tau"], precision=prec)
+        try:
+            x, (i2,) = p2.solve(b, restart=c["restart"], rtol=c["rtol"], flexible=True)
+            assert i2.status == 0 and i2.true_relres <= c["rtol"], (prec, i2)
+            assert abs(i2.iterations - ref["iters"]) <= 2, (prec, i2.iterations, ref["iters"])
+        finally:
+            p2.close()
+
+
+def test_c2_full_size():
+    # 2D upwind convection-diffusion 1024^2 with ILUT(1e-3, 10) +
+    # SAIT_Thr(1e-3, 4) (n = 1,048,576): factors bit for bit, the autotuned
+    # FP64 apply bit for bit (or within the wavefront bound), GMRES(50) to
+    # 1e-8 within one step of the oracle
+    print("[test_c2_full_size] building", flush=True)
+    c = config("c2")
+    A = c["A"]
+    L, U = oracle.ilut(A, c["ilut_tau"], c["ilut_fill"])
+    ML, MU = oracle.sait_factors(L, U, c["m"], tau=c["tau"])
+    pre = SaitPreconditioner(A, m=c["m"], tau=c["tau"], ilu_kind="ilut", ilut_tau=c["ilut_tau"],
+                             ilut_fill=c["ilut_fill"])
+    try:
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, _ = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v, ref.v)
+        lanes = pre.autotune()
+        r = uniform_vector(A.n, 12)
+        z = pre.apply(_t(r)).cpu().numpy()
+        zr = oracle.apply(ML, MU, r)
+        if all(x in (-64, -65, -8, -16) for x in lanes):
+            np.testing.assert_array_equal(z, zr)
+        else:
+            assert np.linalg.norm(z - zr) <= 1e-12 * np.linalg.norm(zr)
+        x, (info,) = pre.solve(_t(c["b"]), restart=c["restart"], rtol=c["rtol"])
+        ref = oracle.gmres(A, c["b"], ("sait64", ML, MU), restart=c["restart"], rtol=c["rtol"])
+        assert info.status == 0 and info.true_relres <= c["rtol"], info
+        assert abs(info.iterations - ref["iters"]) <= 1, (info.iterations, ref["iters"])
+    finally:
+        pre.close()
