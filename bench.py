@@ -23,7 +23,8 @@ eigenpairs of the same matrix, SAIT_Thr(0.01, 10) block preconditioning,
 beside the exact solves and none): steps, seconds, error against the
 closed-form spectrum.  `parilu_experiment`: the ILU factors built on the
 device by fine-grained parallel ILU sweeps: build time and PCG iterations
-against the host ILU(0).
+against the host ILU(0).  `ratio_experiment`: nnz(M_L)/nnz(L) against m for
+tau = 0, 0.01, 0.02, 0.05 (the curves of Sec. 4.1).
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -374,6 +375,31 @@ def paper_experiment(torch, dev):
     return out
 
 
+def ratio_experiment(torch, dev):
+    """The ratio r = nnz(M_L) / nnz(L) of SAIT_Thr(tau, m) against the number
+    of passes m = 1..10 for tau = 0, 0.01, 0.02, 0.05 on the level-0 ILU
+    factor of the paper's 100^3 Laplacian (the curves of Sec. 4.1; with
+    tau = 0 nothing is dropped and the ratio grows with the reach of
+    T~^m, with tau > 0 it settles), with the build time of each factor pair."""
+    from paper_2106_12836_amd import SaitPreconditioner
+    from workloads import poisson3d
+
+    A = poisson3d(100)
+    out = dict(workload="3D 7-point Laplace 100^3, level-0 ILU, SAIT_Thr(tau, m) of L and U")
+    for tau in (0.0, 0.01, 0.02, 0.05):
+        rows = []
+        for m in range(1, 11):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pre = SaitPreconditioner(A, m=m, tau=tau)
+            torch.cuda.synchronize()
+            rows.append(dict(m=m, ratio_L=round(pre.query()["ratio_L"], 4), build_s=round(time.perf_counter() - t0, 3)))
+            pre.close()
+        out[f"tau_{tau}"] = rows
+    print(f"[bench] ratio curves: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def parilu_experiment(torch, dev):
     """ILU factors built on the device by synchronous fixed-point sweeps
     (fine-grained parallel ILU) instead of the row-wise host ILU(0), on the
@@ -488,6 +514,7 @@ def main():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's PCG experiment (100^3)")
     ap.add_argument("--no-eigen", action="store_true", help="skip the paper's LOBPCG experiment (100^3)")
     ap.add_argument("--no-parilu", action="store_true", help="skip the device ILU (ParILU) experiment (100^3)")
+    ap.add_argument("--no-ratio", action="store_true", help="skip the nonzero-ratio curves (100^3)")
     ap.add_argument("--parilu-only", action="store_true",
                     help="run only the device ILU (ParILU) experiment and print its record (for profiling)")
     ap.add_argument("--eigen-only", action="store_true",
@@ -625,6 +652,9 @@ def main():
     parilu = None
     if not args.no_parilu:
         parilu = parilu_experiment(torch, dev)
+    ratio = None
+    if not args.no_ratio:
+        ratio = ratio_experiment(torch, dev)
 
     batched = None
     if not args.no_batched:
@@ -666,6 +696,7 @@ def main():
         "paper_experiment": paper,
         "eigen_experiment": eigen,
         "parilu_experiment": parilu,
+        "ratio_experiment": ratio,
     }
     print(json.dumps(line), flush=True)
 

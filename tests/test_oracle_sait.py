@@ -241,3 +241,16 @@ def test_pattern_variant_equals_power_pattern(orc):
             # SAIT_Pat(p, m) never leaves that pattern
             Mp = orc.sait_pat(T, p, 5)
             assert not np.any((_dense(Mp) != 0) & ~Pp)
+
+
+def test_interior_row_count_without_dropping(orc):
+    # 3D 7-point stencil, tau = 0: an interior row of M_m (m passes) holds
+    # every column reachable by at most m steps back along x, y or z, i.e.
+    # (m+1)(m+2)(m+3)/6 entries (the tau = 0 curve of Sec. 4.1)
+    s = 13
+    A = poisson3d(s)
+    L, U = orc.ilu0(A)
+    c = (s // 2) * (1 + s + s * s)  # the centre point
+    for m in range(1, 6):
+        M = orc.sait_thr(L, 0.0, m)
+        assert M.rp[c + 1] - M.rp[c] == (m + 1) * (m + 2) * (m + 3) // 6, m
