@@ -23,8 +23,9 @@ eigenpairs of the same matrix, SAIT_Thr(0.01, 10) block preconditioning,
 beside the exact solves and none): steps, seconds, error against the
 closed-form spectrum.  `parilu_experiment`: the ILU factors built on the
 device by fine-grained parallel ILU sweeps: build time and PCG iterations
-against the host ILU(0).  `ratio_experiment`: nnz(M_L)/nnz(L) against m for
-tau = 0, 0.01, 0.02, 0.05 (the curves of Sec. 4.1).
+against the host ILU(0).  `curves_experiment`: ratio, PCG iterations and
+seconds against m for SAIT_Thr / SAIT_Pat and against tau at m = 10 (the
+curves of Sec. 4.1-4.2).
 
 Algorithmic bytes of one apply (s_v = value bytes, s_y = bytes of the
 intermediate vector y = M_L r: 8 for FP64, 4 for the binary32 forms):
@@ -375,28 +376,49 @@ def paper_experiment(torch, dev):
     return out
 
 
-def ratio_experiment(torch, dev):
-    """The ratio r = nnz(M_L) / nnz(L) of SAIT_Thr(tau, m) against the number
-    of passes m = 1..10 for tau = 0, 0.01, 0.02, 0.05 on the level-0 ILU
-    factor of the paper's 100^3 Laplacian (the curves of Sec. 4.1; with
-    tau = 0 nothing is dropped and the ratio grows with the reach of
-    T~^m, with tau > 0 it settles), with the build time of each factor pair."""
+def curves_experiment(torch, dev):
+    """The curves of Sec. 4.1-4.2 on the paper's 100^3 Laplacian, for the
+    level-0 and level-1 ILU factors: for SAIT_Thr(tau, m), tau = 0.01, 0.02,
+    0.05, and SAIT_Pat(p, m), p = 1, 2, 3, with m = 1..10, the ratio
+    nnz(M_L) / nnz(L), the PCG iterations to 1e-10 (f ~ U[0, 1), seed 0)
+    and the seconds per solve; the nonzero ratio without dropping (tau = 0)
+    for m = 1..10; and SAIT_Thr(tau, 10) over a wider range of tau (level 0)
+    for the runtime optimum of Sec. 4.2."""
     from paper_2106_12836_amd import SaitPreconditioner
     from workloads import poisson3d
 
     A = poisson3d(100)
-    out = dict(workload="3D 7-point Laplace 100^3, level-0 ILU, SAIT_Thr(tau, m) of L and U")
-    for tau in (0.0, 0.01, 0.02, 0.05):
-        rows = []
-        for m in range(1, 11):
+    f = torch.tensor(np.random.default_rng(0).uniform(0.0, 1.0, A.n), dtype=torch.float64, device=dev)
+
+    def point(solve=True, **opts):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pre = SaitPreconditioner(A, **opts)
+        torch.cuda.synchronize()
+        rec = dict(ratio_L=round(pre.query()["ratio_L"], 4), build_s=round(time.perf_counter() - t0, 3))
+        if solve:
+            pre.solve(f, rtol=1e-10, method="pcg")  # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            pre = SaitPreconditioner(A, m=m, tau=tau)
+            x, (info,) = pre.solve(f, rtol=1e-10, method="pcg", maxit=3000)
             torch.cuda.synchronize()
-            rows.append(dict(m=m, ratio_L=round(pre.query()["ratio_L"], 4), build_s=round(time.perf_counter() - t0, 3)))
-            pre.close()
-        out[f"tau_{tau}"] = rows
-    print(f"[bench] ratio curves: {out}", file=sys.stderr, flush=True)
+            rec.update(iterations=info.iterations, seconds=round(time.perf_counter() - t0, 4), status=info.status)
+        pre.close()
+        return rec
+
+    out = dict(workload="3D 7-point Laplace 100^3, SAIT of the level-0 / level-1 ILU factors, PCG to 1e-10, "
+                        "f ~ U[0,1) (seed 0)")
+    for level in (0, 1):
+        ilu = {} if level == 0 else dict(ilu_kind="iluk", ilu_level=1)
+        for tau in (0.01, 0.02, 0.05):
+            out[f"level{level}_thr_{tau}"] = [dict(m=m, **point(m=m, tau=tau, **ilu)) for m in range(1, 11)]
+        for pp in (1, 2, 3):
+            out[f"level{level}_pat_{pp}"] = [dict(m=m, **point(m=m, pattern_p=pp, **ilu)) for m in range(1, 11)]
+        print(f"[bench] curves level {level} done", file=sys.stderr, flush=True)
+    out["level0_thr_0_ratio"] = [dict(m=m, **point(solve=False, m=m, tau=0.0)) for m in range(1, 11)]
+    out["level0_thr_m10"] = [dict(tau=t, **point(m=10, tau=t))
+                             for t in (0.1, 0.05, 0.03, 0.02, 0.01, 0.005, 0.003, 0.002, 0.001, 0.0)]
+    print("[bench] curves done", file=sys.stderr, flush=True)
     return out
 
 
@@ -514,7 +536,7 @@ def main():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's PCG experiment (100^3)")
     ap.add_argument("--no-eigen", action="store_true", help="skip the paper's LOBPCG experiment (100^3)")
     ap.add_argument("--no-parilu", action="store_true", help="skip the device ILU (ParILU) experiment (100^3)")
-    ap.add_argument("--no-ratio", action="store_true", help="skip the nonzero-ratio curves (100^3)")
+    ap.add_argument("--no-curves", action="store_true", help="skip the ratio / iteration curves (100^3)")
     ap.add_argument("--parilu-only", action="store_true",
                     help="run only the device ILU (ParILU) experiment and print its record (for profiling)")
     ap.add_argument("--eigen-only", action="store_true",
@@ -652,9 +674,9 @@ def main():
     parilu = None
     if not args.no_parilu:
         parilu = parilu_experiment(torch, dev)
-    ratio = None
-    if not args.no_ratio:
-        ratio = ratio_experiment(torch, dev)
+    curves = None
+    if not args.no_curves:
+        curves = curves_experiment(torch, dev)
 
     batched = None
     if not args.no_batched:
@@ -696,7 +718,7 @@ def main():
         "paper_experiment": paper,
         "eigen_experiment": eigen,
         "parilu_experiment": parilu,
-        "ratio_experiment": ratio,
+        "curves_experiment": curves,
     }
     print(json.dumps(line), flush=True)
 
