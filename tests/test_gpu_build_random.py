@@ -1,0 +1,85 @@
+"""Randomised parity of the device SAIT build: seeded random diagonally
+dominant matrices of varied size, bandwidth and density (ragged sizes that
+are not multiples of the 64-row slices, rows whose candidate counts cross
+the LDS size tiers), each with random settings of the ILU (ILU(0), ILU(k),
+ILUT, the device ILU), m, tau, the side of the upper factor's recursion,
+the per-row cap, the pattern rule and the storage precision.  The ILU
+factors, M_L, M_U and their stored values must equal the oracle's bit for
+bit."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_12836_amd import SaitPreconditioner
+from workloads import random_diag_dominant
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(50, 3000))
+    k_off = int(rng.integers(2, 12))
+    band = None if rng.random() < 0.3 else int(rng.integers(5, max(6, n // 4)))
+    A = random_diag_dominant(n, k_off, band=band, seed=seed)
+    opts = dict(m=int(rng.integers(0, 6)), tau=float(rng.choice([0.0, 1e-3, 1e-2, 5e-2, 0.2])),
+                upper_side=str(rng.choice(["left", "right"])))
+    opts["precision"] = str(rng.choice(["f64", "f64", "f32", "bf16"]))
+    kind = str(rng.choice(["ilu0", "ilu0", "iluk", "ilut", "parilu"]))
+    opts["ilu_kind"] = kind
+    if kind == "iluk":
+        opts["ilu_level"] = int(rng.integers(1, 3))
+    elif kind == "ilut":
+        opts["ilut_tau"] = float(rng.choice([1e-4, 1e-3, 1e-2]))
+        opts["ilut_fill"] = int(rng.integers(2, 12))
+    elif kind == "parilu":
+        opts["ilu_level"] = int(rng.integers(0, 2))
+        opts["parilu_sweeps"] = int(rng.integers(0, 4))
+    r = rng.random()
+    if r < 0.25:
+        opts["max_nnz_row"] = int(rng.integers(2, 12))
+    elif r < 0.45:
+        opts["pattern_p"] = int(rng.integers(0, 4))
+        opts["tau"] = 0.0
+    return A, opts
+
+
+def _oracle_ilu(A, o):
+    kind = o["ilu_kind"]
+    if kind == "iluk":
+        return oracle.iluk(A, o["ilu_level"])
+    if kind == "ilut":
+        return oracle.ilut(A, o["ilut_tau"], o["ilut_fill"])
+    if kind == "parilu":
+        return oracle.parilu(A, o["parilu_sweeps"], o["ilu_level"])
+    return oracle.ilu0(A)
+
+
+@pytest.mark.parametrize("seed", range(64))
+def test_random_build_matches_oracle(seed):
+    A, opts = _case(seed)
+    print(f"[test_random_build_matches_oracle] seed={seed} n={A.n} nnz={A.nnz} {opts}", flush=True)
+    L, U = _oracle_ilu(A, opts)
+    ML, MU = oracle.sait_factors(L, U, opts["m"], tau=opts["tau"], cap=opts.get("max_nnz_row", 0),
+                                 p=opts.get("pattern_p", -1), upper_side=opts["upper_side"])
+    pre = SaitPreconditioner(A, **opts)
+    try:
+        for which, ref in (("L", L), ("U", U)):
+            rp, ci, v = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v, ref.v)
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, stored = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp, err_msg=which)
+            np.testing.assert_array_equal(ci, ref.ci, err_msg=which)
+            np.testing.assert_array_equal(v.view(np.uint64), ref.v.view(np.uint64), err_msg=which)
+            if opts["precision"] == "f32":
+                np.testing.assert_array_equal(stored.view(np.uint32), oracle.round_f32(ref.v).view(np.uint32))
+            elif opts["precision"] == "bf16":
+                np.testing.assert_array_equal(stored.view(np.uint16), oracle.round_bf16(ref.v))
+            else:
+                np.testing.assert_array_equal(stored.view(np.uint64), ref.v.view(np.uint64))
+    finally:
+        pre.close()
