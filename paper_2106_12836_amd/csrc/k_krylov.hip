@@ -10,11 +10,14 @@
 // process is classical Gram-Schmidt with delayed re-orthogonalisation
 // (dcgs2_finalize): one step is
 //   z = M u_j, w = A z                    (SAIT apply, any storage precision)
-//   one pass: V^T u, V^T w, u.u, u.w      (k_dots2; the last block completes
-//                                          column j-1 and the coefficients)
+//   one pass: V^T u, V^T w, u.u, u.w      (k_dots2, per-block partials)
+//   one block: sums, column j-1 of H and the coefficients (k_dots2_fin)
 //   one pass: q_j and u_{j+1}             (k_update2)
-// Reductions are deterministic: each block writes a partial, the last block
-// to finish (atomic ticket) sums the partials in a fixed order.  Every
+// Reductions are deterministic: each block writes a partial and a one-block
+// kernel sums the partials in a fixed order.  A second launch costs less
+// than an atomic ticket taken by every block of the pass (the ticket's
+// agent-scope release writes back each XCD's L2 once per block: measured
+// 15.8 against 8.5 us for a 2-vector pass over 2^21 rows in 512 blocks).  Every
 // kernel of an Arnoldi step starts by reading the `done` flag, so steps
 // enqueued after convergence cost only a launch; the host keeps a few steps
 // queued ahead and polls a pinned, device-written mailbox to stop
@@ -58,29 +61,13 @@ __device__ __forceinline__ double block_sum(double x, double *sh) {
     return r;
 }
 
-__device__ __forceinline__ bool last_block(unsigned *counter) {
-    __shared__ int am_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    return am_last != 0;
-}
-
-__device__ __forceinline__ double ld_acq(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Reduce part[i*B + b] over b for i < count into out[i] (last block only).
-__device__ void reduce_partials(const double *part, int B, int count, double *out, double *sh) {
-    for (int i = 0; i < count; ++i) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < B; b += kNT) s += ld_acq(part + (size_t)i * B + b);
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) out[i] = s;
-    }
+// Sum of part[0 .. B) in a fixed order (one block; the result is valid in
+// thread 0): thread t adds the partials t, t + kNT, ... in turn, then the
+// block sum.
+__device__ double sum_partials(const double *part, int B, double *sh) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < B; b += kNT) s += part[b];
+    return block_sum(s, sh);
 }
 
 struct Rows {
@@ -272,11 +259,10 @@ __device__ __forceinline__ void dots_rows(const double *const (&vp)[8], const do
 
 // Partial inner products of one Arnoldi step (nq = j basis vectors, u = V_j,
 // w = A M u_j or null at the closing step), per block into part[idx * B +
-// block] with idx = i (V_i.u), k + i (V_i.w), 2k (u.u), 2k + 1 (u.w); the
-// last block to finish sums them in block order and runs dcgs2_finalize.
+// block] with idx = i (V_i.u), k + i (V_i.w), 2k (u.u), 2k + 1 (u.w).
 __global__ __launch_bounds__(kNT) void k_dots2(int64_t n, const double *__restrict__ V, int64_t ldv, int nq,
                                                const double *__restrict__ u, const double *__restrict__ w,
-                                               GmresDev *st, double *part, unsigned *counter, Mailbox *mb) {
+                                               const GmresDev *st, double *part) {
     constexpr int kSl = 18;
     __shared__ double sh[4 * kSl];
     if (st->done) return;
@@ -321,10 +307,18 @@ __global__ __launch_bounds__(kNT) void k_dots2(int64_t n, const double *__restri
         }
         __syncthreads();
     }
-    if (!last_block(counter)) return;
+}
+
+// The sums of k_dots2's partials over its B blocks (in block order) and
+// dcgs2_finalize; one block.  full: w was present (not the closing step).
+__global__ __launch_bounds__(kNT) void k_dots2_fin(int nq, int full, int B, GmresDev *st, const double *part,
+                                                   Mailbox *mb) {
+    __shared__ double sh[8];
+    if (st->done) return;
+    const int k = st->restart;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // each wavefront reduces 4 values at a time: lanes take blocks (all loads
-    // of the 4 values in flight together), then a fixed butterfly per value.
-    // Plain loads: the ticket of last_block acquired the other blocks' partials.
+    // of the 4 values in flight together), then a fixed butterfly per value
     const int nvals = 2 * nq + 2;
     auto value_index = [&](int v) {
         if (v < nq) return v;
@@ -354,14 +348,13 @@ __global__ __launch_bounds__(kNT) void k_dots2(int64_t n, const double *__restri
             const double tv = wave_sum(t[g]);
             if (lane == 0 && v0 + g < nvals) {
                 const int idx = value_index(v0 + g);
-                if (w || !(idx == 2 * k + 1 || (idx >= k && idx < 2 * k))) st->red[idx] = tv;
+                if (full || !(idx == 2 * k + 1 || (idx >= k && idx < 2 * k))) st->red[idx] = tv;
             }
         }
     }
-    if (!w && threadIdx.x == 0) st->red[2 * k + 1] = 0.0;
+    if (!full && threadIdx.x == 0) st->red[2 * k + 1] = 0.0;
     __syncthreads();
-    if (threadIdx.x == 0) *counter = 0;
-    dcgs2_finalize(st, nq, w != nullptr, mb, sh);
+    dcgs2_finalize(st, nq, full != 0, mb, sh);
 }
 
 // Update of step j (skipped once the cycle is done):
@@ -419,39 +412,39 @@ __global__ __launch_bounds__(kNT) void k_update2(int64_t n, double *__restrict__
     }
 }
 
-// ||r||^2 of the residual in V[0]; the last block starts a cycle:
-// beta, g = beta e_1, jc = 0, done unless more iterations are needed.
-// mode 0: r = b (computes ||b||); mode 1: cycle start.
-__global__ __launch_bounds__(kNT) void k_cycle_norm(int64_t n, const double *__restrict__ r, GmresDev *st, int mode,
-                                                    double *part, unsigned *counter, Mailbox *mb) {
+// Partials of ||r||^2 per block (k_cycle_norm_fin sums them).
+__global__ __launch_bounds__(kNT) void k_cycle_norm(int64_t n, const double *__restrict__ r, double *part) {
     __shared__ double sh[4];
-    const int B = gridDim.x;
-    const Rows R = block_rows(n, B);
+    const Rows R = block_rows(n, gridDim.x);
     double a = 0;
     for (int64_t i = R.lo + threadIdx.x; i < R.hi; i += kNT) a = fma(r[i], r[i], a);
     const double s = block_sum(a, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (!last_block(counter)) return;
-    double ss = 0;
-    reduce_partials(part, B, 1, &ss, sh);
-    if (threadIdx.x == 0) {
-        *counter = 0;
-        const double nrm = sqrt(ss);
-        if (mode == 0) {
-            st->nb = nrm;
-        } else {
-            st->beta = nrm;
-            st->g[0] = nrm;
-            for (int i = 1; i <= st->restart; ++i) st->g[i] = 0.0;
-            st->jc = 0;
-            const bool ok = st->nb == 0.0 || nrm / st->nb <= st->rtol;
-            st->done = (ok || st->iters >= st->maxit) ? 1 : 0;
-            if (mb) {
-                mb->iters = st->iters;
-                __threadfence_system();
-                __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
-        }
+}
+
+// ||r|| from the B partials (one block).  mode 0: r = b (sets ||b||);
+// mode 1: r is the residual in V[0]: beta, g = beta e_1, jc = 0, done
+// unless more iterations are needed.
+__global__ __launch_bounds__(kNT) void k_cycle_norm_fin(int B, GmresDev *st, int mode, const double *part,
+                                                        Mailbox *mb) {
+    __shared__ double sh[4];
+    const double ss = sum_partials(part, B, sh);
+    if (threadIdx.x != 0) return;
+    const double nrm = sqrt(ss);
+    if (mode == 0) {
+        st->nb = nrm;
+        return;
+    }
+    st->beta = nrm;
+    st->g[0] = nrm;
+    for (int i = 1; i <= st->restart; ++i) st->g[i] = 0.0;
+    st->jc = 0;
+    const bool ok = st->nb == 0.0 || nrm / st->nb <= st->rtol;
+    st->done = (ok || st->iters >= st->maxit) ? 1 : 0;
+    if (mb) {
+        mb->iters = st->iters;
+        __threadfence_system();
+        __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -531,14 +524,16 @@ __global__ void k_init_state(GmresDev *st, int restart, int maxit, double rtol) 
 //   ||r|| / ||b|| <= rtol, z = M r, beta = (r, z)_new / (r, z)_old,
 //   p = z + beta p.
 // Each kernel reads `done` first; the reductions are per-block partials
-// summed by the last block in block order.
+// summed in block order by a one-block kernel (k_pcg_fin).
 // ---------------------------------------------------------------------------
 
-// Partial sums of x.y (and u.w if u) of the block's rows into part[0 / 1][blk];
-// returns true in the last block, whose thread 0 then holds the totals.
-__device__ bool pcg_dots(int64_t n, const double *x, const double *y, const double *u, const double *w, double *part,
-                         unsigned *counter, double &t0, double &t1) {
+// Partial sums of x.y (and u.w if u) of the block's rows into part[0 / 1][blk].
+// check_done: skip once the iteration has stopped.
+__global__ __launch_bounds__(kNT) void k_pcg_dots(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                                                  const double *__restrict__ u, const double *__restrict__ w,
+                                                  const PcgDev *st, int check_done, double *part) {
     __shared__ double sh[4];
+    if (check_done && st->done) return;
     const int B = gridDim.x;
     const Rows R = block_rows(n, B);
     double a = 0.0, c = 0.0;
@@ -552,45 +547,6 @@ __device__ bool pcg_dots(int64_t n, const double *x, const double *y, const doub
         part[blockIdx.x] = a;
         if (u) part[B + blockIdx.x] = c;
     }
-    if (!last_block(counter)) return false;
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < B; b += kNT) {
-        s0 += part[b];
-        if (u) s1 += part[B + b];
-    }
-    t0 = block_sum(s0, sh);
-    t1 = u ? block_sum(s1, sh) : 0.0;
-    if (threadIdx.x == 0) *counter = 0;
-    return true;
-}
-
-// ||b||, ||r0||: start of the iteration (done when b = 0 or already converged)
-__global__ __launch_bounds__(kNT) void k_pcg_start(int64_t n, const double *__restrict__ b, const double *__restrict__ r,
-                                                   PcgDev *st, double *part, unsigned *counter, Mailbox *mb) {
-    double bb, rr;
-    if (!pcg_dots(n, b, b, r, r, part, counter, bb, rr)) return;
-    if (threadIdx.x != 0) return;
-    st->nb = sqrt(bb);
-    st->relres = st->nb > 0.0 ? sqrt(rr) / st->nb : 0.0;
-    st->iters = 0;
-    st->breakdown = 0;
-    st->done = (st->nb == 0.0 || st->relres <= st->rtol || st->maxit == 0) ? 1 : 0;
-    if (mb) {
-        mb->iters = 0;
-        __threadfence_system();
-        __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-}
-
-// (r, z): rz on the first call, beta = rz_new / rz afterwards
-__global__ __launch_bounds__(kNT) void k_pcg_rz(int64_t n, const double *__restrict__ r, const double *__restrict__ z,
-                                                PcgDev *st, int first, double *part, unsigned *counter) {
-    if (st->done) return;
-    double rz, unused;
-    if (!pcg_dots(n, r, z, nullptr, nullptr, part, counter, rz, unused)) return;
-    if (threadIdx.x != 0) return;
-    if (!first) st->beta = rz / st->rz;
-    st->rz = rz;
 }
 
 // p = z (first) or p = z + beta p
@@ -602,35 +558,14 @@ __global__ void k_pcg_dir(int64_t n, const double *__restrict__ z, double *__res
         p[i] = first ? z[i] : fma(beta, p[i], z[i]);
 }
 
-// alpha = (r, z) / (p, q); (p, q) = 0 ends the iteration (breakdown)
-__global__ __launch_bounds__(kNT) void k_pcg_alpha(int64_t n, const double *__restrict__ p,
-                                                   const double *__restrict__ q, PcgDev *st, double *part,
-                                                   unsigned *counter, Mailbox *mb) {
-    if (st->done) return;
-    double pq, unused;
-    if (!pcg_dots(n, p, q, nullptr, nullptr, part, counter, pq, unused)) return;
-    if (threadIdx.x != 0) return;
-    if (pq == 0.0) {
-        st->breakdown = 1;
-        st->done = 1;
-        if (mb) {
-            __threadfence_system();
-            __hip_atomic_store(&mb->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-        return;
-    }
-    st->alpha = st->rz / pq;
-}
-
-// x += alpha p, r -= alpha q, ||r||: count the iteration, decide convergence
+// x += alpha p, r -= alpha q, partials of ||r||^2
 __global__ __launch_bounds__(kNT) void k_pcg_xr(int64_t n, const double *__restrict__ p, const double *__restrict__ q,
-                                                double *__restrict__ x, double *__restrict__ r, PcgDev *st,
-                                                double *part, unsigned *counter, Mailbox *mb) {
+                                                double *__restrict__ x, double *__restrict__ r, const PcgDev *st,
+                                                double *part) {
     __shared__ double sh[4];
     if (st->done) return;
     const double alpha = st->alpha;
-    const int B = gridDim.x;
-    const Rows R = block_rows(n, B);
+    const Rows R = block_rows(n, gridDim.x);
     double a = 0.0;
     for (int64_t i = R.lo + threadIdx.x; i < R.hi; i += kNT) {
         x[i] = fma(alpha, p[i], x[i]);
@@ -640,29 +575,71 @@ __global__ __launch_bounds__(kNT) void k_pcg_xr(int64_t n, const double *__restr
     }
     a = block_sum(a, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = a;
-    if (!last_block(counter)) return;
-    double s0 = 0.0;
-    for (int b = threadIdx.x; b < B; b += kNT) s0 += part[b];
-    const double rr = block_sum(s0, sh);
-    if (threadIdx.x != 0) return;
-    *counter = 0;
-    st->iters += 1;
-    st->relres = sqrt(rr) / st->nb;
-    st->done = (st->relres <= st->rtol || st->iters >= st->maxit) ? 1 : 0;
-    if (mb) {
-        mb->iters = st->iters;
-        mb->est = st->relres;
-        __threadfence_system();
-        __hip_atomic_store(&mb->done, st->done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
 }
 
-// ||res||^2 into true_rr (res = b - A x at the end)
-__global__ __launch_bounds__(kNT) void k_pcg_true(int64_t n, const double *__restrict__ res, PcgDev *st, double *part,
-                                                  unsigned *counter) {
-    double rr, unused;
-    if (!pcg_dots(n, res, res, nullptr, nullptr, part, counter, rr, unused)) return;
-    if (threadIdx.x == 0) st->true_rr = rr;
+enum PcgStep : int { kPcgStart, kPcgRz, kPcgRzFirst, kPcgAlpha, kPcgXr, kPcgTrue };
+
+__device__ void pcg_post(Mailbox *mb, int done, const PcgDev *st, bool progress) {
+    if (!mb) return;
+    if (progress) {
+        mb->iters = st->iters;
+        mb->est = st->relres;
+    }
+    __threadfence_system();
+    __hip_atomic_store(&mb->done, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// The scalar part of a PCG step from the B partials of the preceding pass
+// (one block, sums in block order):
+//   kPcgStart: ||b|| and ||r0|| (done when b = 0 or already converged)
+//   kPcgRz / kPcgRzFirst: (r, z); beta = rz_new / rz except on the first call
+//   kPcgAlpha: alpha = (r, z) / (p, q); (p, q) = 0 ends the iteration
+//   kPcgXr: ||r||: count the iteration, decide convergence
+//   kPcgTrue: ||b - A x||^2 into true_rr
+__global__ __launch_bounds__(kNT) void k_pcg_fin(int step, int B, PcgDev *st, const double *part, Mailbox *mb) {
+    __shared__ double sh[4];
+    if ((step == kPcgRz || step == kPcgRzFirst || step == kPcgAlpha || step == kPcgXr) && st->done) return;
+    const double t0 = sum_partials(part, B, sh);
+    const double t1 = step == kPcgStart ? sum_partials(part + B, B, sh) : 0.0;
+    if (threadIdx.x != 0) return;
+    switch (step) {
+    case kPcgStart:
+        st->nb = sqrt(t0);
+        st->relres = st->nb > 0.0 ? sqrt(t1) / st->nb : 0.0;
+        st->iters = 0;
+        st->breakdown = 0;
+        st->done = (st->nb == 0.0 || st->relres <= st->rtol || st->maxit == 0) ? 1 : 0;
+        if (mb) mb->iters = 0;
+        pcg_post(mb, st->done, st, false);
+        return;
+    case kPcgRz:
+        st->beta = t0 / st->rz;
+        st->rz = t0;
+        return;
+    case kPcgRzFirst:
+        st->rz = t0;
+        return;
+    case kPcgAlpha:
+        if (t0 == 0.0) {
+            st->breakdown = 1;
+            st->done = 1;
+            pcg_post(mb, 1, st, false);
+            return;
+        }
+        st->alpha = st->rz / t0;
+        return;
+    case kPcgXr:
+        st->iters += 1;
+        st->relres = sqrt(t0) / st->nb;
+        st->done = (st->relres <= st->rtol || st->iters >= st->maxit) ? 1 : 0;
+        pcg_post(mb, st->done, st, true);
+        return;
+    case kPcgTrue:
+        st->true_rr = t0;
+        return;
+    default:
+        return;
+    }
 }
 
 __global__ void k_pcg_init(PcgDev *st, int maxit, double rtol) {
@@ -724,8 +701,6 @@ void Solver::ensure(Allocator *a, int64_t n, int restart, bool flexible, int pre
     arr_.alloc(a, sizeof(double) * (2 * hsz + (flexible ? kk * kk : 0) + 9 * (kk + 2) + 2 * kk + 2));
     st_.alloc(a, sizeof(GmresDev));
     part_.alloc(a, sizeof(double) * (size_t)512 * (2 * kk + 2));
-    counters_.alloc(a, 4 * sizeof(unsigned));
-    SAIT_HIP(hipMemset(counters_.as<void>(), 0, 4 * sizeof(unsigned)));
     if (!mailbox_) SAIT_HIP(hipHostMalloc(&mailbox_, 256, hipHostMallocMapped));
     // bind the array pointers inside the device state
     GmresDev h{};
@@ -800,10 +775,6 @@ int Solver::pcg(Allocator *a, const Ops &ops, const double *b, double *x, const 
         pq_.alloc(a, nn);
         pst_.alloc(a, sizeof(PcgDev));
         ppart_.alloc(a, sizeof(double) * 2 * 1024);
-        if (counters_.empty()) {
-            counters_.alloc(a, 4 * sizeof(unsigned));
-            SAIT_HIP(hipMemset(counters_.as<void>(), 0, 4 * sizeof(unsigned)));
-        }
         if (!mailbox_) SAIT_HIP(hipHostMalloc(&mailbox_, 256, hipHostMallocMapped));
         pn_ = n;
     }
@@ -813,13 +784,18 @@ int Solver::pcg(Allocator *a, const Ops &ops, const double *b, double *x, const 
     SAIT_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&mbd), mailbox_, 0));
     double *r = pr_.as<double>(), *z = pz_.as<double>(), *p = pp_.as<double>(), *q = pq_.as<double>();
     double *part = ppart_.as<double>();
-    unsigned *cnt = counters_.as<unsigned>();
     const int RB = std::min(reduce_blocks(n), 1024);
+    // a reduction: RB partial sums, then the scalar step on one block
+    auto reduce = [&](int step, const double *x1, const double *y1, const double *u1, const double *w1,
+                      int check_done, Mailbox *mb) {
+        hipLaunchKernelGGL(k_pcg_dots, dim3(RB), dim3(kNT), 0, s, n, x1, y1, u1, w1, st, check_done, part);
+        hipLaunchKernelGGL(k_pcg_fin, dim3(1), dim3(kNT), 0, s, step, RB, st, part, mb);
+    };
     const int SB = stream_blocks(n);
 
     hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1), 0, s, st, o.maxit, o.rtol);
     spmv(*ops.A, x, XKind::F64, r, YKind::F64, 1, 1, 1, ops.lanesA, s, b);  // r = b - A x
-    hipLaunchKernelGGL(k_pcg_start, dim3(RB), dim3(kNT), 0, s, n, b, r, st, part, cnt, mbd);
+    reduce(kPcgStart, b, b, r, r, 0, mbd);
     SAIT_LAUNCH_CHECK();
     PcgDev hs{};
     SAIT_HIP(hipMemcpyAsync(&hs, st, sizeof(PcgDev), hipMemcpyDeviceToHost, s));
@@ -832,7 +808,7 @@ int Solver::pcg(Allocator *a, const Ops &ops, const double *b, double *x, const 
     }
     if (!hs.done) {
         apply_prec(ops, r, z, s);
-        hipLaunchKernelGGL(k_pcg_rz, dim3(RB), dim3(kNT), 0, s, n, r, z, st, 1, part, cnt);
+        reduce(kPcgRzFirst, r, z, nullptr, nullptr, 1, nullptr);
         hipLaunchKernelGGL(k_pcg_dir, dim3(SB), dim3(256), 0, s, n, z, p, st, 1);
         SAIT_LAUNCH_CHECK();
         // iterations, a few queued ahead of the polled mailbox
@@ -842,10 +818,11 @@ int Solver::pcg(Allocator *a, const Ops &ops, const double *b, double *x, const 
         bool stop = false;
         for (int it = 0; it < o.maxit && !stop; ++it) {
             spmv(*ops.A, p, XKind::F64, q, YKind::F64, 1, 1, 1, ops.lanesA, s);
-            hipLaunchKernelGGL(k_pcg_alpha, dim3(RB), dim3(kNT), 0, s, n, p, q, st, part, cnt, mbd);
-            hipLaunchKernelGGL(k_pcg_xr, dim3(RB), dim3(kNT), 0, s, n, p, q, x, r, st, part, cnt, mbd);
+            reduce(kPcgAlpha, p, q, nullptr, nullptr, 1, mbd);
+            hipLaunchKernelGGL(k_pcg_xr, dim3(RB), dim3(kNT), 0, s, n, p, q, x, r, st, part);
+            hipLaunchKernelGGL(k_pcg_fin, dim3(1), dim3(kNT), 0, s, (int)kPcgXr, RB, st, part, mbd);
             apply_prec(ops, r, z, s);
-            hipLaunchKernelGGL(k_pcg_rz, dim3(RB), dim3(kNT), 0, s, n, r, z, st, 0, part, cnt);
+            reduce(kPcgRz, r, z, nullptr, nullptr, 1, nullptr);
             hipLaunchKernelGGL(k_pcg_dir, dim3(SB), dim3(256), 0, s, n, z, p, st, 0);
             SAIT_LAUNCH_CHECK();
             SAIT_HIP(hipEventRecord(ev[it % (kAhead + 1)], s));
@@ -858,7 +835,7 @@ int Solver::pcg(Allocator *a, const Ops &ops, const double *b, double *x, const 
     }
     // true residual
     spmv(*ops.A, x, XKind::F64, q, YKind::F64, 1, 1, 1, ops.lanesA, s, b);
-    hipLaunchKernelGGL(k_pcg_true, dim3(RB), dim3(kNT), 0, s, n, q, st, part, cnt);
+    reduce(kPcgTrue, q, q, nullptr, nullptr, 0, nullptr);
     SAIT_LAUNCH_CHECK();
     SAIT_HIP(hipMemcpyAsync(&hs, st, sizeof(PcgDev), hipMemcpyDeviceToHost, s));
     SAIT_HIP(hipStreamSynchronize(s));
@@ -883,7 +860,6 @@ int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, cons
     SAIT_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&mbd), mailbox_, 0));
     double *V = V_.as<double>();
     double *part = part_.as<double>();
-    unsigned *cnt = counters_.as<unsigned>();
     const int RB = reduce_blocks(n);
     const int SB = stream_blocks(n);
     const int UB = update_blocks(n);
@@ -891,7 +867,8 @@ int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, cons
     hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, st, k, o.maxit, o.rtol);
     SAIT_LAUNCH_CHECK();
     // ||b||
-    hipLaunchKernelGGL(k_cycle_norm, dim3(RB), dim3(kNT), 0, s, n, b, st, 0, part, cnt, (Mailbox *)nullptr);
+    hipLaunchKernelGGL(k_cycle_norm, dim3(RB), dim3(kNT), 0, s, n, b, part);
+    hipLaunchKernelGGL(k_cycle_norm_fin, dim3(1), dim3(kNT), 0, s, RB, st, 0, part, (Mailbox *)nullptr);
     SAIT_LAUNCH_CHECK();
     GmresDev hs{};
     int restarts = 0;
@@ -899,7 +876,8 @@ int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, cons
     for (;;) {
         // r = b - A x  -> V[0], beta, cycle reset
         spmv(*ops.A, x, XKind::F64, V, YKind::F64, 1, 1, 1, ops.lanesA, s, b);
-        hipLaunchKernelGGL(k_cycle_norm, dim3(RB), dim3(kNT), 0, s, n, V, st, 1, part, cnt, mbd);
+        hipLaunchKernelGGL(k_cycle_norm, dim3(RB), dim3(kNT), 0, s, n, V, part);
+        hipLaunchKernelGGL(k_cycle_norm_fin, dim3(1), dim3(kNT), 0, s, RB, st, 1, part, mbd);
         SAIT_LAUNCH_CHECK();
         SAIT_HIP(hipMemcpyAsync(&hs, st, sizeof(GmresDev), hipMemcpyDeviceToHost, s));
         SAIT_HIP(hipStreamSynchronize(s));
@@ -935,7 +913,8 @@ int Solver::solve(Allocator *a, const Ops &ops, const double *b, double *x, cons
                 apply_prec(ops, uj, zj, s);
                 spmv(*ops.A, zj, XKind::F64, w, YKind::F64, 1, 1, 1, ops.lanesA, s);
             }
-            hipLaunchKernelGGL(k_dots2, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j, uj, w, st, part, cnt, mbd);
+            hipLaunchKernelGGL(k_dots2, dim3(RB), dim3(kNT), 0, s, n, V, ldv_, j, uj, w, st, part);
+            hipLaunchKernelGGL(k_dots2_fin, dim3(1), dim3(kNT), 0, s, j, (int)(w != nullptr), RB, st, part, mbd);
             if (j < k) hipLaunchKernelGGL(k_update2, dim3(UB), dim3(kNT), 0, s, n, V, ldv_, j, st);
             SAIT_LAUNCH_CHECK();
             SAIT_HIP(hipEventRecord(ev[j % (kAhead + 1)], s));

@@ -56,7 +56,7 @@ class Solver {
     int64_t n_ = -1, ldv_ = 0;
     int restart_ = 0;
     bool flex_ = false;
-    DevBuf V_, Z_, zt_, ut_, y32_, arr_, st_, part_, counters_;
+    DevBuf V_, Z_, zt_, ut_, y32_, arr_, st_, part_;
     DevBuf pt1_, pt2_;                      // preconditioner scratch (Jacobi sweeps, exact solves)
     DevBuf pr_, pz_, pp_, pq_, pst_, ppart_;  // PCG vectors, state, partial sums
     int64_t pn_ = -1;
