@@ -319,8 +319,9 @@ void sait_default_eig_opts(sait_eig_opts *o);
  * for the whole n x k residual block, two sparse matrix-matrix products) and
  * A W, forms the Gram matrices of the trial basis [X, W, P] on the device
  * and solves its Rayleigh-Ritz problem (order <= 3k) on the host: if the
- * unit-diagonal scaled S^T S has a Cholesky pivot <= 1e-14 that step drops
- * P, and if [X, W] fails too the solve stops with SAIT_BREAKDOWN.
+ * unit-diagonal scaled S^T S of [X, W, P] has a Cholesky pivot <= 1e-8 that
+ * step drops P, and if [X, W] has one <= 1e-14 the solve stops with
+ * SAIT_BREAKDOWN.
  * A must be symmetric and the preconditioner symmetric positive definite
  * (SAIT with upper_side = SAIT_SIDE_RIGHT on a symmetric A is); neither is
  * checked.  Single-system handles only.

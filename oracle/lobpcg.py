@@ -21,25 +21,33 @@ gradient (SIAM J. Sci. Comput. 23 (2001)), written out plainly in FP64:
       X <- S c;  P <- [W, P] c_(W,P)  (the part of the update outside X)
   AX, AW, AP are carried along so that A multiplies only W.
 
-If the scaled G_B has a Cholesky pivot L_jj^2 <= PIVOT_MIN (the basis is
-numerically dependent), that step is redone without P; if [X, W] also
-fails the solve stops with status 2.
+If the scaled G_B of [X, W, P] has a Cholesky pivot L_jj^2 <= PIVOT_P (the
+basis is close to dependent), that step is redone without P; if the pivot
+of [X, W] falls to PIVOT_MIN the solve stops with status 2.
 """
 
 import numpy as np
 import scipy.linalg as sla
 
+# Rayleigh-Ritz on a basis whose scaled Gram matrix has condition number c
+# loses about log10(c) digits.  [X, W, P] is accepted only while its
+# smallest pivot stays above PIVOT_P: with pivots near 1e-10 the Ritz values
+# of a clustered spectrum drifted below the smallest eigenvalue of an SPD
+# matrix and the iteration diverged.  [X, W] (and the start block) only has
+# to stay above PIVOT_MIN: near convergence W is small and noisy, and a
+# stricter bound there would stop the iteration one step short.
 PIVOT_MIN = 1e-14
+PIVOT_P = 1e-8
 
 
-def _cholesky_lower(B):
+def _cholesky_lower(B, pivot_min=PIVOT_MIN):
     """Plain Cholesky B = L L^T (column by column); None when a pivot
-    L_jj^2 <= PIVOT_MIN."""
+    L_jj^2 <= pivot_min."""
     m = B.shape[0]
     L = np.zeros_like(B)
     for j in range(m):
         s = B[j, j] - L[j, :j] @ L[j, :j]
-        if not s > PIVOT_MIN:
+        if not s > pivot_min:
             return None
         L[j, j] = np.sqrt(s)
         for i in range(j + 1, m):
@@ -47,13 +55,13 @@ def _cholesky_lower(B):
     return L
 
 
-def rayleigh_ritz(GA, GB, k):
+def rayleigh_ritz(GA, GB, k, pivot_min=PIVOT_MIN):
     """k smallest Ritz pairs of the pencil (G_A, G_B): (theta, coefficients)
-    or None when the scaled G_B is numerically singular."""
+    or None when the scaled G_B has a Cholesky pivot <= pivot_min."""
     d = 1.0 / np.sqrt(np.diag(GB))
     Ah = 0.5 * (GA + GA.T) * np.outer(d, d)
     Bh = GB * np.outer(d, d)
-    L = _cholesky_lower(Bh)
+    L = _cholesky_lower(Bh, pivot_min)
     if L is None:
         return None
     Cm = sla.solve_triangular(L, sla.solve_triangular(L, Ah, lower=True).T, lower=True)
@@ -114,7 +122,7 @@ def lobpcg(A, X0, prec=None, tol=1e-8, maxit=1000):
         for use_p in ((True, False) if P is not None else (False,)):
             S = np.hstack([X, W, P] if use_p else [X, W])
             AS = np.hstack([AX, AW, AP] if use_p else [AX, AW])
-            step = rayleigh_ritz(S.T @ AS, S.T @ S, k)
+            step = rayleigh_ritz(S.T @ AS, S.T @ S, k, PIVOT_P if use_p else PIVOT_MIN)
             if step is not None:
                 break
             p_drops += 1

@@ -301,9 +301,9 @@ void jacobi_eigen(int m, std::vector<double> &C, std::vector<double> &w, std::ve
 
 // k smallest Ritz pairs of (GA, GB) (m x m, leading block of 16 x 16
 // tiles): theta[k], coef (m x k row-major).  false if the unit-diagonal
-// scaled GB has a Cholesky pivot <= kPivotMin.
+// scaled GB has a Cholesky pivot <= pivot_min.
 bool rayleigh_ritz(int m, int k, const double *GA16, const double *GB16, std::vector<double> &theta,
-                   std::vector<double> &coef) {
+                   std::vector<double> &coef, double pivot_min) {
     std::vector<double> d(m), A((size_t)m * m), B((size_t)m * m), L((size_t)m * m, 0.0);
     for (int i = 0; i < m; ++i) {
         const double g = GB16[i * 16 + i];
@@ -318,7 +318,7 @@ bool rayleigh_ritz(int m, int k, const double *GA16, const double *GB16, std::ve
     for (int j = 0; j < m; ++j) {  // B = L L^T
         double s = B[(size_t)j * m + j];
         for (int q = 0; q < j; ++q) s -= L[(size_t)j * m + q] * L[(size_t)j * m + q];
-        if (!(s > kPivotMin)) return false;
+        if (!(s > pivot_min)) return false;
         const double ljj = std::sqrt(s);
         L[(size_t)j * m + j] = ljj;
         for (int i = j + 1; i < m; ++i) {
@@ -469,7 +469,7 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
     gram(1, false);
     readback(false);
     std::vector<double> theta, coef;
-    if (!rayleigh_ritz(k, k, h, h + kGramTile, theta, coef))
+    if (!rayleigh_ritz(k, k, h, h + kGramTile, theta, coef, kPivotMin))
         fail(SAIT_E_INVALID, "LOBPCG: the start block is numerically rank deficient");
     update(1, theta, coef);
 
@@ -493,11 +493,11 @@ int Lobpcg::run(Allocator *alloc, int64_t n, int k, double *X, const BlockOp &ap
         if (it == o.maxit) break;
         // the [X, W] pencil is the leading 2k x 2k part of the [X, W, P] tiles
         int use = nb;
-        bool ok = rayleigh_ritz(use * k, k, h, h + kGramTile, theta, coef);
+        bool ok = rayleigh_ritz(use * k, k, h, h + kGramTile, theta, coef, use == 3 ? kPivotP : kPivotMin);
         if (!ok && use == 3) {
             ++p_drops;
             use = 2;
-            ok = rayleigh_ritz(use * k, k, h, h + kGramTile, theta, coef);
+            ok = rayleigh_ritz(use * k, k, h, h + kGramTile, theta, coef, kPivotMin);
         }
         if (!ok) {
             status = 2;

@@ -11,8 +11,15 @@ namespace sait {
 using BlockOp = std::function<void(const double *X, double *Y, hipStream_t s)>;
 
 // Smallest admissible Cholesky pivot L_jj^2 of the unit-diagonal scaled
-// S^T S; below it the trial basis counts as numerically dependent.
+// S^T S: kPivotP for [X, W, P] (below it the step drops P), kPivotMin for
+// [X, W] and the start block (below it the basis counts as numerically
+// dependent).  The Rayleigh-Ritz values lose about as many digits as the
+// basis condition number has: with [X, W, P] pivots near 1e-10 a clustered
+// spectrum's Ritz values drifted below the smallest eigenvalue and the
+// iteration diverged; near convergence W is small and noisy, and the
+// stricter bound on [X, W] would stop the iteration one step short.
 constexpr double kPivotMin = 1e-14;
+constexpr double kPivotP = 1e-8;
 
 class Lobpcg {
   public:

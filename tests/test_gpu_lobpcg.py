@@ -215,3 +215,56 @@ def test_lobpcg_smallest_problem():
         np.testing.assert_allclose(lam, ref["lam"], rtol=1e-12)
     finally:
         pre.close()
+
+
+def _random_spd(rng, seed):
+    import scipy.sparse as sp
+    from workloads import Csr, random_diag_dominant
+
+    kind = str(rng.choice(["sym-rdd", "aniso", "poisson2d", "poisson3d"]))
+    if kind == "sym-rdd":
+        n = int(rng.integers(100, 1200))
+        R = random_diag_dominant(n, int(rng.integers(2, 6)), band=int(rng.integers(4, max(5, n // 8))),
+                                 seed=seed).to_scipy()
+        off = R - sp.diags(R.diagonal())
+        S = (off + off.T).tocsr()
+        S = S + sp.diags(1.0 + np.asarray(abs(S).sum(axis=1)).ravel())
+        return kind, Csr.from_scipy(sp.csr_matrix(S))
+    if kind == "aniso":
+        return kind, aniso2d(int(rng.integers(10, 36)), float(rng.choice([0.05, 0.2, 1.0])))
+    if kind == "poisson2d":
+        return kind, poisson2d(int(rng.integers(10, 36)))
+    return kind, poisson3d(int(rng.integers(5, 11)))
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_lobpcg_random_matches_oracle(seed):
+    # seeded SPD matrices, block sizes 1..5 and preconditioners; same bar as
+    # test_lobpcg_matches_oracle
+    torch = _torch()
+    rng = np.random.default_rng(4000 + seed)
+    kind, A = _random_spd(rng, seed)
+    k = int(rng.integers(1, 6))
+    pk = str(rng.choice(["sait", "sait", "jacobi", "none", "exact"]))
+    m, tau, sweeps = int(rng.integers(1, 6)), float(rng.choice([1e-3, 1e-2, 5e-2])), int(rng.integers(1, 4))
+    level = int(rng.integers(0, 2)) if pk == "sait" else 0
+    print(f"[test_lobpcg_random_matches_oracle] seed={seed} {kind} n={A.n} k={k} {pk} m={m} tau={tau} "
+          f"sweeps={sweeps} level={level}", flush=True)
+    X0 = _start(A.n, k, 10 + seed)
+    ref = oracle.lobpcg(A, X0, _oracle_prec(A, pk, tau=tau, m=m, sweeps=sweeps, level=level), tol=1e-8, maxit=3000)
+    assert ref["status"] == 0
+    build = dict(m=m, tau=tau)
+    if level:
+        build.update(ilu_kind="iluk", ilu_level=level)
+    pre = SaitPreconditioner(A, **build)
+    try:
+        if pk != "sait":
+            pre.set_preconditioner(pk, sweeps)
+        lam, X, info = pre.lobpcg(torch.tensor(X0, device="cuda:0"), tol=1e-8, maxit=3000)
+        print(f"  device {info}, oracle iterations {ref['iters']}", flush=True)
+        assert info["status"] == 0, info
+        np.testing.assert_allclose(lam, ref["lam"], rtol=1e-10)
+        assert abs(info["iterations"] - ref["iters"]) <= max(3, 0.1 * ref["iters"]), (info, ref["iters"])
+        _check_block(pre, lam, X, 1e-8)
+    finally:
+        pre.close()
