@@ -149,3 +149,41 @@ def test_batched_c4_full_size():
             ref = oracle.gmres(As, B[s0:s1, q], ("sait64", ML, MU), restart=c["restart"], rtol=c["rtol"])
             assert abs(infos[s * R + q].iterations - ref["iters"]) <= 1, (s, q, infos[s * R + q].iterations,
                                                                           ref["iters"])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_batched_random_matches_oracle(seed):
+    # seeded batches: 1-16 systems of random kind and size (anisotropic
+    # diffusion with log-uniform eps, Poisson, random diagonally dominant),
+    # 1-11 right-hand sides with an occasional zero column, random restart,
+    # rtol, m and tau; every pair against the oracle's solve of its block
+    from workloads import poisson2d, random_diag_dominant
+
+    rng = np.random.default_rng(5000 + seed)
+    blocks = []
+    for i in range(int(rng.integers(1, 17))):
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            blocks.append(aniso2d(int(rng.integers(3, 31)), float(10.0 ** rng.uniform(-3, 0))))
+        elif kind == 1:
+            blocks.append(poisson2d(int(rng.integers(3, 31))))
+        else:
+            blocks.append(random_diag_dominant(int(rng.integers(5, 900)), int(rng.integers(1, 7)),
+                                               band=int(rng.integers(2, 40)), seed=100 * seed + i))
+    A, sys_ptr = block_diag(blocks)
+    nrhs = int(rng.integers(1, 12))
+    restart = int(rng.choice([3, 5, 10, 20, 30]))
+    rtol = float(rng.choice([1e-6, 1e-8, 1e-10]))
+    m, tau = int(rng.integers(1, 5)), float(rng.choice([1e-3, 1e-2, 5e-2]))
+    B = uniform_vector(A.n, 20 + seed, k=nrhs)
+    if nrhs > 1 and rng.random() < 0.5:
+        B[:, int(rng.integers(0, nrhs))] = 0.0
+    print(f"[test_batched_random_matches_oracle] seed={seed} nsys={len(blocks)} n={A.n} nrhs={nrhs} "
+          f"restart={restart} rtol={rtol} m={m} tau={tau}", flush=True)
+    pre = SaitPreconditioner(A, nsys=len(blocks), sys_ptr=sys_ptr, m=m, tau=tau)
+    try:
+        X, infos = pre.solve(torch.tensor(B, device=DEV), restart=restart, rtol=rtol, maxit=5000)
+        torch.cuda.synchronize()
+        _check(A, sys_ptr, B, X.cpu().numpy(), infos, tau, m, restart, rtol, nrhs)
+    finally:
+        pre.close()
