@@ -10,7 +10,10 @@ oracle applies the same roundings), the true residual at most rtol.
 PCG (the paper's solver, Sec. 4) on symmetric matrices with the SAIT,
 Jacobi, exact and no preconditioner, level-0 or level-1 ILU: iteration
 counts within one, the true residual at most 1.5 rtol (PCG stops on the
-recursively updated residual)."""
+recursively updated residual).
+Adjoint (the backward of the differentiable solve): A^T lam = g by
+(F)GMRES with the transposed factors, iteration counts within one and the
+gradient on A's pattern bit for bit the oracle's for the same lam."""
 
 import numpy as np
 import pytest
@@ -136,3 +139,37 @@ def test_random_pcg_matches_oracle(seed):
     assert info.status == 0
     assert abs(info.iterations - ref["iters"]) <= 1, (info.iterations, ref["iters"])
     assert info.true_relres <= 1.5 * rtol
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_adjoint_matches_oracle(seed):
+    # the adjoint solve A^T lam = g with the transposed factors
+    # (z = M_L^T (M_U^T r)) and the gradient on A's pattern, on seeded
+    # nonsymmetric matrices and settings
+    rng = np.random.default_rng(7000 + seed)
+    kind, A = _matrix(rng, seed)
+    m, tau = int(rng.integers(1, 5)), float(rng.choice([1e-3, 1e-2, 5e-2]))
+    side = str(rng.choice(["left", "right"]))
+    restart, flexible = int(rng.choice([10, 20, 30])), bool(rng.random() < 0.5)
+    g = rng.uniform(-1.0, 1.0, A.n)
+    print(f"[test_random_adjoint_matches_oracle] seed={seed} {kind} n={A.n} m={m} tau={tau} side={side} "
+          f"restart={restart} flexible={flexible}", flush=True)
+    L, U = oracle.ilu0(A)
+    ML, MU = oracle.sait_factors(L, U, m, tau=tau, upper_side=side)
+    ref = oracle.gmres(oracle.transpose(A), g, ("sait64", oracle.transpose(MU), oracle.transpose(ML)),
+                       restart=restart, rtol=1e-10, flexible=flexible, maxit=5000)
+    assert ref["status"] == 0
+    pre = SaitPreconditioner(A, m=m, tau=tau, upper_side=side, build_transpose=1)
+    try:
+        lam, (info,) = pre.solve(_t(g), transpose=True, restart=restart, rtol=1e-10, flexible=flexible, maxit=5000)
+        lam_np = lam.cpu().numpy()
+        x = rng.uniform(-1.0, 1.0, A.n)
+        gv = pre.grad_values(_t(lam_np), _t(x)).cpu().numpy()
+    finally:
+        pre.close()
+    print(f"  device {info.iterations} oracle {ref['iters']}", flush=True)
+    assert info.status == 0
+    assert abs(info.iterations - ref["iters"]) <= 1, (info.iterations, ref["iters"])
+    r = g - A.to_scipy().T @ lam_np
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(g) * (1 + 1e-7)
+    np.testing.assert_array_equal(gv, oracle.grad_values(A, lam_np, x))
