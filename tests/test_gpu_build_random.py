@@ -83,3 +83,41 @@ def test_random_build_matches_oracle(seed):
                 np.testing.assert_array_equal(stored.view(np.uint64), ref.v.view(np.uint64))
     finally:
         pre.close()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_device_ilu_symmetric_matches_oracle(seed):
+    # the symmetric (incomplete Cholesky) form of the device ILU on seeded
+    # symmetric diagonally dominant matrices: level 0 or 1 pattern, 0-4
+    # sweeps, then SAIT with random m, tau; factors and M_L, M_U bit for bit
+    import scipy.sparse as sp
+    from workloads import Csr
+
+    rng = np.random.default_rng(8000 + seed)
+    n = int(rng.integers(50, 3000))
+    R = random_diag_dominant(n, int(rng.integers(2, 8)), band=None if rng.random() < 0.3 else
+                             int(rng.integers(4, max(5, n // 4))), seed=seed).to_scipy()
+    off = R - sp.diags(R.diagonal())
+    S = (off + off.T).tocsr()
+    S = S + sp.diags(1.0 + np.asarray(abs(S).sum(axis=1)).ravel())
+    A = Csr.from_scipy(sp.csr_matrix(S))
+    level, sweeps = int(rng.integers(0, 2)), int(rng.integers(0, 5))
+    m, tau = int(rng.integers(0, 5)), float(rng.choice([0.0, 1e-3, 1e-2, 5e-2]))
+    print(f"[test_random_device_ilu_symmetric_matches_oracle] seed={seed} n={A.n} nnz={A.nnz} level={level} "
+          f"sweeps={sweeps} m={m} tau={tau}", flush=True)
+    L, U = oracle.paric(A, sweeps, level)
+    ML, MU = oracle.sait_factors(L, U, m, tau=tau)
+    pre = SaitPreconditioner(A, m=m, tau=tau, ilu_kind="paric", ilu_level=level, parilu_sweeps=sweeps)
+    try:
+        for which, ref in (("L", L), ("U", U)):
+            rp, ci, v = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v.view(np.uint64), ref.v.view(np.uint64), err_msg=which)
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, _ = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp, err_msg=which)
+            np.testing.assert_array_equal(ci, ref.ci, err_msg=which)
+            np.testing.assert_array_equal(v.view(np.uint64), ref.v.view(np.uint64), err_msg=which)
+    finally:
+        pre.close()
