@@ -265,12 +265,14 @@ const char *sait_last_error(void);
  *     chunks;
  *   a power of two 1..64: wavefront CSR with that many lanes per row.
  * The sliced-ELL and LDS-staged kernels compute each row as the left-to-
- * right sum of separately rounded products in column order.  Blocks of
- * right-hand sides always use the wavefront kernel (8 lanes per row for a
- * negative shape).  sait_autotune times every candidate on the handle's
- * factors and A (device work on hip_stream, synchronises it) and keeps the
- * fastest; sait_set_apply_lanes overrides (0 = keep); sait_get_apply_lanes
- * reports.
+ * right sum of separately rounded products in column order.  Blocks of 2-5
+ * or 8 right-hand sides with a negative shape use the sliced-ELL block
+ * kernel (one row per lane, the same sums per column, so every column equals
+ * the one-vector product bit for bit); other block widths use the wavefront
+ * kernel (8 lanes per row for a negative shape).  sait_autotune times every
+ * candidate on the handle's factors and A (device work on hip_stream,
+ * synchronises it) and keeps the fastest; sait_set_apply_lanes overrides
+ * (0 = keep); sait_get_apply_lanes reports.
  */
 #define SAIT_SHAPE_SELL (-64)
 #define SAIT_SHAPE_STREAM (-16)

@@ -103,3 +103,40 @@ def test_random_apply_matches_oracle(seed):
                     np.testing.assert_array_equal(Z[:, k], zo)
     finally:
         pre.close()
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_tiny_random_build_apply_solve(seed):
+    # n from 1 to 130 (one partial slice, exactly 64 / 128 rows, one row
+    # past a slice): factors bit for bit, the apply on every exact shape bit
+    # for bit, GMRES within one iteration of the oracle
+    rng = np.random.default_rng(9000 + seed)
+    n = int(rng.choice([1, 2, 3, 63, 64, 65, 127, 128, 129, int(rng.integers(4, 130))]))
+    A = random_diag_dominant(n, int(rng.integers(1, 6)), band=None, seed=seed)
+    m, tau = int(rng.integers(0, 5)), float(rng.choice([0.0, 1e-2, 5e-2]))
+    side = str(rng.choice(["left", "right"]))
+    print(f"[test_tiny_random_build_apply_solve] seed={seed} n={n} nnz={A.nnz} m={m} tau={tau} side={side}",
+          flush=True)
+    L, U = oracle.ilu0(A)
+    ML, MU = oracle.sait_factors(L, U, m, tau=tau, upper_side=side)
+    r = uniform_vector(n, 60 + seed)
+    pre = SaitPreconditioner(A, m=m, tau=tau, upper_side=side)
+    try:
+        for which, ref in (("ML", ML), ("MU", MU)):
+            rp, ci, v, _ = pre.export(which)
+            np.testing.assert_array_equal(rp, ref.rp)
+            np.testing.assert_array_equal(ci, ref.ci)
+            np.testing.assert_array_equal(v.view(np.uint64), ref.v.view(np.uint64))
+        zr = oracle.apply(ML, MU, r)
+        for shape in (-64, -65, -8, -16):
+            sait_set_apply_lanes(pre.handle, shape, shape)
+            np.testing.assert_array_equal(pre.apply(_t(r)).cpu().numpy(), zr)
+        sait_set_apply_lanes(pre.handle, -64, -64)
+        b = A.to_scipy() @ uniform_vector(n, 80 + seed)
+        ref = oracle.gmres(A, b, ("sait64", ML, MU), restart=10, rtol=1e-10)
+        x, (info,) = pre.solve(_t(b), restart=10, rtol=1e-10)
+        assert info.status == 0 and ref["status"] == 0
+        assert abs(info.iterations - ref["iters"]) <= 1, (info.iterations, ref["iters"])
+        assert np.linalg.norm(b - A.to_scipy() @ x.cpu().numpy()) <= 1e-10 * np.linalg.norm(b) * (1 + 1e-7)
+    finally:
+        pre.close()
