@@ -18,10 +18,11 @@
 // than an atomic ticket taken by every block of the pass (the ticket's
 // agent-scope release writes back each XCD's L2 once per block: measured
 // 15.8 against 8.5 us for a 2-vector pass over 2^21 rows in 512 blocks).  Every
-// kernel of an Arnoldi step starts by reading the `done` flag, so steps
-// enqueued after convergence cost only a launch; the host keeps a few steps
-// queued ahead and polls a pinned, device-written mailbox to stop
-// enqueueing.  The host synchronises once per restart cycle, to read the
+// Krylov kernel of an Arnoldi step starts by reading the `done` flag; the
+// preconditioner and operator products do not, so each of the (at most
+// three) steps enqueued after convergence still costs those products.  The
+// host keeps a few steps queued ahead and polls a pinned, device-written
+// mailbox to stop enqueueing.  The host synchronises once per restart cycle, to read the
 // true residual.
 #include <hip/hip_runtime.h>
 
@@ -523,8 +524,9 @@ __global__ void k_init_state(GmresDev *st, int restart, int maxit, double rtol) 
 //   alpha = (r, z) / (p, q), x += alpha p, r -= alpha q, stop once
 //   ||r|| / ||b|| <= rtol, z = M r, beta = (r, z)_new / (r, z)_old,
 //   p = z + beta p.
-// Each kernel reads `done` first; the reductions are per-block partials
-// summed in block order by a one-block kernel (k_pcg_fin).
+// Each PCG kernel reads `done` first (the preconditioner and operator
+// products do not); the reductions are per-block partials summed in block
+// order by a one-block kernel (k_pcg_fin).
 // ---------------------------------------------------------------------------
 
 // Partial sums of x.y (and u.w if u) of the block's rows into part[0 / 1][blk].
