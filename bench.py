@@ -8,7 +8,8 @@ apply divided by the measured time per step (GB/s), beside the fraction of
 the 8 TB/s HBM peak.  The second half of the metric -- time to a 1e-10
 true relative residual with FGMRES(40), FP32 / BF16 factors against the
 FP64 form -- is measured after the timed loop and reported in
-`time_to_residual`.  `batched` reports the batched workload (256 anisotropic
+`time_to_residual` (also to 1e-8, the residual the metric's name quotes,
+under `rtol_1e-8`).  `batched` reports the batched workload (256 anisotropic
 2D systems x 8 right-hand sides, GMRES(30) to 1e-8, one persistent launch):
 wall time, systems/s, pair-iterations/s and the modelled bytes per second
 (batched_bytes).  `other_workloads`: FP64 apply GB/s on the random
@@ -653,6 +654,19 @@ def main():
         for prec in ("f32", "bf16"):
             ttr[prec]["speedup_vs_f64"] = round(base / ttr[prec]["seconds"], 3)
         ttr["method"] = "FGMRES(40), FP64 basis/dots/Hessenberg/true residual, rtol 1e-10, x0 = 0, b = A x_true"
+        # the same solves to 1e-8, the residual the metric's name quotes
+        r8 = {}
+        for prec, p in pres.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = p.solve(b, restart=40, rtol=1e-8, flexible=True)
+            torch.cuda.synchronize()
+            r8[prec] = dict(seconds=round(time.perf_counter() - t0, 4), iterations=info[0].iterations,
+                            true_relres=info[0].true_relres, status=info[0].status)
+        for prec in ("f32", "bf16"):
+            r8[prec]["speedup_vs_f64"] = round(r8["f64"]["seconds"] / r8[prec]["seconds"], 3)
+        ttr["rtol_1e-8"] = r8
+        print(f"[bench] solves to 1e-8: {r8}", file=sys.stderr, flush=True)
 
     for p in pres.values():
         p.close()
