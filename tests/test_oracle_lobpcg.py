@@ -10,7 +10,9 @@ experiment) against what the mathematics fixes:
     test-side LOBPCG that keeps the previous iterate instead of P gives the
     same Ritz values step by step;
   * a trial space of full dimension gives the exact eigenpairs at once;
-  * X is orthonormal and diagonalises A on exit.
+  * X is orthonormal and diagonalises A on exit;
+  * on a clustered spectrum every Ritz value stays above lambda_min (the
+    P-drop bound of 1e-8; with 1e-14 the iteration diverged).
 """
 
 import numpy as np
@@ -130,3 +132,28 @@ def test_rank_deficient_start_rejected():
     X0[:, 1] = X0[:, 0]
     with pytest.raises(ValueError):
         oracle.lobpcg(A, X0)
+
+
+def test_clustered_spectrum_stays_above_lambda_min():
+    # a symmetric diagonally dominant matrix whose 2nd..6th eigenvalues lie
+    # within 5 % of each other, k = 4, SAIT_Thr(1e-3, 3): the trial basis
+    # [X, W, P] becomes nearly dependent.  Cauchy interlacing forbids a Ritz
+    # value below lambda_min; with P kept down to a pivot of 1e-14 the Ritz
+    # values fell below it and the iteration diverged.  Dropping P below
+    # 1e-8 keeps every Ritz value above lambda_min and converges to LAPACK's
+    # eigenvalues.
+    from workloads import random_diag_dominant
+
+    R = random_diag_dominant(750, 4, band=73, seed=2).to_scipy()
+    off = R - sp.diags(R.diagonal())
+    S = (off + off.T).tocsr()
+    S = S + sp.diags(1.0 + np.asarray(abs(S).sum(axis=1)).ravel())
+    A = Csr.from_scipy(sp.csr_matrix(S))
+    ev = sla.eigh(S.toarray(), eigvals_only=True)
+    assert ev[5] - ev[1] < 0.05 * ev[1]
+    L, U = oracle.ilu0(A)
+    out = oracle.lobpcg(A, _start(A.n, 4, 12), ("sait64", *oracle.sait_factors(L, U, 3, tau=1e-3)), tol=1e-8,
+                        maxit=3000)
+    assert out["status"] == 0 and out["p_drops"] > 0
+    assert np.all(np.asarray(out["theta_hist"])[:, 0] >= ev[0] * (1 - 1e-12))
+    np.testing.assert_allclose(out["lam"], ev[:4], rtol=1e-10)
