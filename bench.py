@@ -118,7 +118,7 @@ def copy_bandwidth(torch, dev, mib=1024, reps=20):
     return 2 * mib * 2**20 / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(A, tau, m, target_seconds=12.0):
+def cpu_baseline(A, tau, m, target_seconds=10.0):
     """The CPU oracle's FP64 apply on the host cores (bounded sample)."""
     import oracle
 
@@ -130,7 +130,7 @@ def cpu_baseline(A, tau, m, target_seconds=12.0):
     oracle.apply(ML, MU, r)  # warm
     reps, t = 0, 0.0
     t0 = time.time()
-    while reps < 2 or (time.time() - t0 < target_seconds and reps < 200):
+    while reps < 2 or (time.time() - t0 < target_seconds and reps < 5000):
         oracle.apply(ML, MU, r)
         reps += 1
     t = (time.time() - t0) / reps
